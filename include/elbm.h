@@ -1,0 +1,194 @@
+/*
+ * elbm.h -- C ABI of the MI355X (gfx950) library for the per-time-step
+ * lattice update of the entropic lattice Boltzmann model for charged
+ * leaky-dielectric multiphase fluids (Lauricella et al., arXiv:1612.05404).
+ *
+ * One step (Sec. II.C, "Summary of the model") on a D3Q19 lattice with one
+ * or two Shan-Chen components:
+ *   streaming of Eq. lattice-b by pulling, halfway bounce-back at walls;
+ *   free charge from Eq. surface-q2 (conserving) or Eq. surface-q3
+ *   (generator-connected), with the curvature of Eq. surface-curvature;
+ *   Poisson equation div(eps grad phi) = -q (Sec. II, Gauss law) by red-black
+ *   SOR with a neutralising uniform charge;
+ *   electric force Eq. force_el2; Shan-Chen force Eq. sc;
+ *   entropic alpha from Eqs. entropic and H (FP64 Newton per node);
+ *   Carreau viscosity, Eqs. strain2 and carreau, and beta from Eq. beta;
+ *   collision Eq. lattice-b with the exact-difference source Eq. add.
+ *
+ * Conventions.
+ *  - Every call returns an elbm_status (0 = ok, < 0 = error); nothing throws
+ *    or aborts across the ABI.  elbm_last_error() gives a message.
+ *  - Host arrays are caller-owned, FP64, C order with x fastest:
+ *    a scalar field is [nz][ny][nx], a component field [C][nz][ny][nx],
+ *    a vector field [3][nz][ny][nx], populations [C][19][nz][ny][nx].
+ *  - D3Q19 order: p = 0 rest; 1..6 = +x, -x, +y, -y, +z, -z;
+ *    7..18 = (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1),
+ *    (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1).
+ *    Opposite directions sit at adjacent (odd, even) indices.
+ *  - Node-type byte: bits 0-1 = 0 fluid, 1 solid wall, 2 inlet, 3 outlet;
+ *    bit 2 = potential fixed (Dirichlet node of the Poisson problem).
+ *  - Device memory: the caller allocates one arena of elbm_required_bytes()
+ *    bytes and passes it with a HIP stream to elbm_bind().  The library never
+ *    allocates device memory; it enqueues all work on that stream.  The arena
+ *    and the stream must outlive the context.  A context is not thread-safe.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELBM_ABI_VERSION 1u
+
+typedef struct elbm_ctx elbm_ctx;
+
+typedef enum {
+    ELBM_OK = 0,
+    ELBM_EINVAL = -1,      /* bad argument: nothing was enqueued            */
+    ELBM_ENOMEM = -2,      /* arena too small or host allocation failed     */
+    ELBM_EHIP = -3,        /* a HIP runtime call failed                     */
+    ELBM_ENONFINITE = -4,  /* a post-collision population became non-finite */
+    ELBM_ESTATE = -7       /* call out of order (e.g. step before bind)     */
+} elbm_status;
+
+enum { ELBM_STORAGE_F64 = 0, ELBM_STORAGE_F32 = 1 };
+enum { ELBM_CHARGE_CONSERVING = 0, ELBM_CHARGE_GENERATOR = 1 };
+enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1 };
+
+/* Model constants shared by every box of a context. */
+typedef struct {
+    int32_t ncomp;            /* 1 (the paper's single fluid) or 2 components       */
+    int32_t storage;          /* ELBM_STORAGE_F64 or _F32 (populations, fields)     */
+    int32_t carreau;          /* 1: Carreau viscosity (Eq. carreau), 0: nu = nu0     */
+    int32_t curvature;        /* 1: surface-charge factor 1 + (K/K_d)^(1/4)          */
+    int32_t electrostriction; /* 1: F_el = qE + (eps-1)/2 grad|E|^2, 0: F_el = qE    */
+    int32_t charge_model;     /* ELBM_CHARGE_*                                      */
+    int32_t sor_sweeps;       /* red-black SOR sweeps per step (>= 0)               */
+    int32_t newton_max;       /* max Newton updates for alpha (>= 1)                */
+    int32_t alpha_guess;      /* ELBM_GUESS_*                                       */
+    int32_t pad_;
+    double G[2][2];           /* Shan-Chen couplings G[s][s'] (Eq. sc)              */
+    double Gw;                /* fluid-wall coupling (Eq. sc)                       */
+    double nu0, nu_inf, lam;  /* viscosity (Newtonian: nu0), Carreau nu_inf, lambda */
+    double K_d;               /* curvature doubling the surface charge              */
+    double rho_th, w_theta;   /* smoothed Heaviside: 0.5(1+tanh((rho-rho_th)/w))    */
+    double xi_b, xi_s;        /* generator-connected charge constants (Eq. surface-q3) */
+    double newton_rtol;       /* alpha converged when |dH| <= rtol * scale          */
+    double rho_in[2];         /* component densities held at inlet nodes            */
+    double rho_out[2];        /* component densities held at outlet nodes           */
+} elbm_params;
+
+/* One lattice box.  Boxes of one context are independent (no exchange). */
+typedef struct {
+    int32_t nx, ny, nz;       /* >= 2 each; a periodic axis must have even length   */
+    int32_t periodic[3];      /* 1 = periodic along x, y, z; 0 = bounded            */
+    double E_ext[3];          /* uniform external field                             */
+    double Q_b, Q_s;          /* bulk and surface charge (conserving model)         */
+    double n_flow;            /* Carreau flow index n                               */
+    double sor_omega;         /* SOR over-relaxation factor in (0, 2)               */
+} elbm_box;
+
+/* Diagnostics of one box, read from the current state. */
+typedef struct {
+    double mass[2];           /* sum over nodes of sum_p f, per component           */
+    double momentum[3];       /* sum over nodes, components and p of c_p f          */
+    double alpha_min, alpha_max, alpha_mean;  /* over fluid nodes, last recorded step */
+    double mean_newton_iters; /* Newton updates per (node, component), all steps    */
+    int64_t n_fallback;       /* alpha fallbacks (no root / no convergence), all steps */
+    int64_t n_negative;       /* negative post-collision populations, all steps     */
+    int64_t n_collisions;     /* (node, component) collisions counted, all steps    */
+} elbm_diag;
+
+/* ABI version of the loaded library (ELBM_ABI_VERSION). */
+uint32_t elbm_abi_version(void);
+
+/* Validates params and boxes (copied), lays out the arena.  *out owns host
+ * memory only; release it with elbm_destroy. */
+elbm_status elbm_create(const elbm_params *params, const elbm_box *boxes, int32_t nboxes,
+                        elbm_ctx **out);
+
+/* Bytes of device memory the context needs in its arena. */
+elbm_status elbm_required_bytes(const elbm_ctx *ctx, size_t *bytes);
+
+/* Binds the caller-owned device arena (256-byte aligned, >= required bytes)
+ * and a hipStream_t (NULL = the null stream).  Uploads the box tables and
+ * clears the counters.  Synchronous. */
+elbm_status elbm_bind(elbm_ctx *ctx, void *dev_arena, size_t bytes, void *hip_stream);
+
+/* Sets the geometry and initial state of one box (synchronous):
+ *  node_type [N] bytes; rho [C][N] initial component densities; u [3][N]
+ *  initial velocity; phi [N] initial potential (Dirichlet nodes keep it);
+ *  u_bc [3][N] inlet velocity (read at inlet nodes only; may be NULL);
+ *  xi [C][19][N] jitter draws (may be NULL = no jitter); jitter amplitude.
+ * Fluid nodes start at f = f_eq(rho, u) (1 + jitter * xi), inlet nodes at
+ * f_eq(rho_in, u_bc), outlet nodes at f_eq(rho_out, 0), solid nodes at 0. */
+elbm_status elbm_set_box(elbm_ctx *ctx, int32_t box, const uint8_t *node_type, const double *rho,
+                         const double *u, const double *phi, const double *u_bc, const double *xi,
+                         double jitter);
+
+/* Enqueues nsteps time steps of every box on the bound stream (asynchronous).
+ * record != 0: the last step also stores the recorded fields (component
+ * densities, half-step velocity, alpha and Newton iterations) that the
+ * elbm_read_* calls return. */
+elbm_status elbm_step(elbm_ctx *ctx, int32_t nsteps, int32_t record);
+
+/* Waits for the stream; returns ELBM_ENONFINITE if any step produced a
+ * non-finite population since bind (sticky). */
+elbm_status elbm_sync(elbm_ctx *ctx);
+
+/* Reads (synchronising first) from the last recorded step:
+ *  rho [C][N] component densities after streaming, u [3][N] half-step
+ *  velocity sum_s (j_s + F_s/2) / sum_s rho_s (Sec. II, after Eq. add). */
+elbm_status elbm_read_moments(elbm_ctx *ctx, int32_t box, double *rho, double *u);
+/* potential phi [N] after the last step's Poisson solve */
+elbm_status elbm_read_potential(elbm_ctx *ctx, int32_t box, double *phi);
+/* free charge q [N] of the last step (without the neutralising background) */
+elbm_status elbm_read_charge(elbm_ctx *ctx, int32_t box, double *q);
+/* alpha [C][N] and Newton updates iters [C][N] (-1 = fallback) of the last
+ * recorded step; zeros at non-fluid nodes.  iters may be NULL. */
+elbm_status elbm_read_alpha(elbm_ctx *ctx, int32_t box, double *alpha, int32_t *iters);
+/* current post-collision populations [C][19][N] (get) / replace them (set) */
+elbm_status elbm_get_populations(elbm_ctx *ctx, int32_t box, double *f);
+elbm_status elbm_set_populations(elbm_ctx *ctx, int32_t box, const double *f);
+/* replaces the potential [N] (warm start of the next solve) */
+elbm_status elbm_set_potential(elbm_ctx *ctx, int32_t box, const double *phi);
+
+/* Conservation and solver diagnostics of one box. */
+elbm_status elbm_diagnostics(elbm_ctx *ctx, int32_t box, elbm_diag *out);
+
+/* Phases of one step for elbm_timing. */
+enum {
+    ELBM_PHASE_DENSITY = 0,   /* pull + component densities                       */
+    ELBM_PHASE_CHARGE = 1,    /* gradient, curvature, charge reductions, Poisson rhs */
+    ELBM_PHASE_POISSON = 2,   /* red-black SOR sweeps (+ zero-mean gauge)          */
+    ELBM_PHASE_EFIELD = 3,    /* |E|^2                                             */
+    ELBM_PHASE_COLLIDE = 4,   /* forces, alpha, rheology, collision                */
+    ELBM_NPHASES = 5
+};
+
+/* Device timing of every phase: enable != 0 records HIP events on the bound
+ * stream around each phase of each following step (a small overhead between
+ * launches); enable == 0 stops and discards.  Host-side events only, no device
+ * memory. */
+elbm_status elbm_set_timing(elbm_ctx *ctx, int32_t enable);
+
+/* Waits for the stream and returns the accumulated device milliseconds per
+ * phase ms[ELBM_NPHASES] and the number of timed steps since timing was
+ * enabled (either pointer may be NULL), then restarts the accumulation. */
+elbm_status elbm_timing(elbm_ctx *ctx, double *ms, int64_t *steps);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *elbm_last_error(const elbm_ctx *ctx);
+
+/* Releases the host state; the arena stays the caller's. */
+void elbm_destroy(elbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELBM_H */
