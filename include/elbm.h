@@ -55,14 +55,18 @@ typedef enum {
     ELBM_ESTATE = -7       /* call out of order (e.g. step before bind)     */
 } elbm_status;
 
-enum { ELBM_STORAGE_F64 = 0, ELBM_STORAGE_F32 = 1 };
+/* Storage: F64 = FP64 populations and fields; F32 = FP32 populations with
+ * FP64 auxiliary fields (densities, psi, charge, potential, |E|^2);
+ * F32_ALL = FP32 populations and fields.  Alpha and the collision moments
+ * are FP64 in every mode. */
+enum { ELBM_STORAGE_F64 = 0, ELBM_STORAGE_F32 = 1, ELBM_STORAGE_F32_ALL = 2 };
 enum { ELBM_CHARGE_CONSERVING = 0, ELBM_CHARGE_GENERATOR = 1 };
 enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1 };
 
 /* Model constants shared by every box of a context. */
 typedef struct {
     int32_t ncomp;            /* 1 (the paper's single fluid) or 2 components       */
-    int32_t storage;          /* ELBM_STORAGE_F64 or _F32 (populations, fields)     */
+    int32_t storage;          /* ELBM_STORAGE_*                                     */
     int32_t carreau;          /* 1: Carreau viscosity (Eq. carreau), 0: nu = nu0     */
     int32_t curvature;        /* 1: surface-charge factor 1 + (K/K_d)^(1/4)          */
     int32_t electrostriction; /* 1: F_el = qE + (eps-1)/2 grad|E|^2, 0: F_el = qE    */

@@ -273,11 +273,13 @@ double ora_carreau_nu(double gd, double nu0, double nu_inf, double lam, double n
  * h(gamma) = rho (2 nu(gamma) + c_s^2) gamma - alpha Pi = 0.  h is strictly
  * increasing for n > 0, h(0) <= 0 and h(hi) >= 0 with
  * hi = alpha Pi / (rho (2 nu_inf + c_s^2)); Newton kept inside the bracket,
- * bisection when it leaves it.
+ * bisection when it leaves it.  Pi = 0 or rho <= 0: gamma = 0 (nu = nu0).
  */
 double ora_shear_rate(double Pn, double rho, double alpha, double nu0, double nu_inf,
                       double lam, double n) {
-    if (Pn <= 0.0) return 0.0;
+    /* no positive root without stress, or at a non-positive density (only
+     * reachable after negative populations): the shear rate is taken as 0 */
+    if (!(Pn > 0.0) || !(rho > 0.0)) return 0.0;
     double lo = 0.0, hi = alpha * Pn / (rho * (2.0 * nu_inf + CS2));
     double g = 0.5 * hi;
     for (int it = 0; it < 200; ++it) {

@@ -1,0 +1,305 @@
+// elbm_device.h -- device-side tables, data structures and per-node maths of
+// the entropic lattice Boltzmann update for charged leaky-dielectric
+// multiphase fluids (Lauricella et al., arXiv:1612.05404), for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "elbm.h"
+
+namespace elbm {
+
+constexpr int NQ = 19;
+constexpr int BLK = 256;
+constexpr int K_FLUID = 0, K_SOLID = 1, K_INLET = 2, K_OUTLET = 3, B_DIRICHLET = 4;
+
+// D3Q19 velocity set (order documented in elbm.h).
+constexpr int kCx[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// weights: the paper's D2Q9 set 4/9, 1/9, 1/36 lifted to D3Q19 (same c_s^2 = 1/3)
+__host__ __device__ constexpr double wgt(int p) {
+  return p == 0 ? 1.0 / 3.0 : (p < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+
+constexpr double CS2 = 1.0 / 3.0;
+
+struct BoxDev {
+  int64_t off;          // first arena node of the box
+  int32_t nx, ny, nz, n;
+  int32_t per[3];
+  int32_t has_dirichlet;
+  int32_t first_block, nblocks, n_unknown, pad;
+  double E[3];
+  double Q_b, Q_s, n_flow, omega;
+};
+
+struct Model {
+  int32_t C, carreau, curvature, electrostriction, charge_model, newton_max;
+  double G[2][2], Gw, nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
+  double rho_in[2], rho_out[2];
+};
+
+// scalars per box: [0] charge scale of the bulk part, [1] of the surface
+// part, [2] neutralising charge qbar, [3] mean potential
+constexpr int NSCAL = 8;
+// counters per box: fallbacks, Newton updates, negative f, non-finite f, collisions
+constexpr int NCNT = 8;
+
+// T: population storage type, F: field storage / stencil arithmetic type
+template <typename T, typename F>
+struct Ptrs {
+  T *fa, *fb;           // populations: read fa, write fb
+  F *rho, *psi, *grad, *bulk, *surf, *q, *phi, *rhs, *e2;
+  F *rec_u;
+  double *rec_alpha;
+  int32_t *rec_iters;
+  uint8_t *type;
+  const BoxDev *boxes;
+  const int32_t *block_box;
+  double *partials;     // [nblocks][4]
+  double *scal;         // [nboxes][NSCAL]
+  unsigned long long *cnt;  // [nboxes][NCNT]
+  uint32_t *err;
+  int64_t N;            // arena nodes (plane stride)
+};
+
+// ------------------------------------------------------------ node decode
+struct Node {
+  BoxDev B;
+  int bb;
+  int64_t g;
+  int n, x, y, z;
+  bool live;
+};
+
+__device__ __forceinline__ void decode(const BoxDev *boxes, const int32_t *block_box, Node &nd) {
+  nd.bb = block_box[blockIdx.x];
+  nd.B = boxes[nd.bb];
+  nd.g = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  nd.n = (int)(nd.g - nd.B.off);
+  nd.live = nd.n < nd.B.n;
+  const int t = nd.live ? nd.n : 0;
+  nd.x = t % nd.B.nx;
+  const int r = t / nd.B.nx;
+  nd.y = r % nd.B.ny;
+  nd.z = r / nd.B.ny;
+}
+
+// local index of r + (dx,dy,dz), wrapping periodic axes; -1 outside the box
+__device__ __forceinline__ int nbr(const BoxDev &B, int x, int y, int z, int dx, int dy, int dz) {
+  int xx = x + dx, yy = y + dy, zz = z + dz;
+  if (xx < 0 || xx >= B.nx) {
+    if (!B.per[0]) return -1;
+    xx = xx < 0 ? xx + B.nx : xx - B.nx;
+  }
+  if (yy < 0 || yy >= B.ny) {
+    if (!B.per[1]) return -1;
+    yy = yy < 0 ? yy + B.ny : yy - B.ny;
+  }
+  if (zz < 0 || zz >= B.nz) {
+    if (!B.per[2]) return -1;
+    zz = zz < 0 ? zz + B.nz : zz - B.nz;
+  }
+  return xx + B.nx * (yy + B.ny * zz);
+}
+
+// --------------------------------------------------------- reductions
+// Fixed-order block sum of K doubles (64-lane wave butterflies, then the
+// four waves in order): bitwise reproducible run to run.
+template <int K>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double *out) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  __shared__ double sm[BLK / 64][K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sm[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = sm[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < BLK / 64; ++w) s += sm[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// -------------------------------------------------------- equilibrium
+// Second-order equilibrium (Sec. II, below Eq. lattice-b).
+template <typename R>
+__device__ __forceinline__ R feq(int p, R rho, R ux, R uy, R uz, R uu) {
+  const R cu = R(kCx[p]) * ux + R(kCy[p]) * uy + R(kCz[p]) * uz;
+  return R(wgt(p)) * rho * (R(1) + cu / R(CS2) + (cu * cu - R(CS2) * uu) / (R(2) * R(CS2) * R(CS2)));
+}
+// f_eq / (w rho) - 1 without cancellation
+__device__ __forceinline__ double feq_dev(int p, double ux, double uy, double uz, double uu) {
+  const double cu = double(kCx[p]) * ux + double(kCy[p]) * uy + double(kCz[p]) * uz;
+  return cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
+}
+
+// phi(y) = (1+y) ln(1+y) - y given l = ln(1+y), cancellation-free: Taylor
+// series sum_{k>=2} (-1)^k y^k / (k(k-1)) through k = 15 for |y| < 1/16
+// (first dropped term below 2e-19 relative), the closed form elsewhere.
+__device__ __forceinline__ double phi_of(double y, double l) {
+  if (fabs(y) < 0.0625) {
+    double s = -1.0 / 210.0;
+    s = fma(s, y, 1.0 / 182.0);
+    s = fma(s, y, -1.0 / 156.0);
+    s = fma(s, y, 1.0 / 132.0);
+    s = fma(s, y, -1.0 / 110.0);
+    s = fma(s, y, 1.0 / 90.0);
+    s = fma(s, y, -1.0 / 72.0);
+    s = fma(s, y, 1.0 / 56.0);
+    s = fma(s, y, -1.0 / 42.0);
+    s = fma(s, y, 1.0 / 30.0);
+    s = fma(s, y, -1.0 / 20.0);
+    s = fma(s, y, 1.0 / 12.0);
+    s = fma(s, y, -1.0 / 6.0);
+    s = fma(s, y, 0.5);
+    return s * y * y;
+  }
+  return (1.0 + y) * l - y;
+}
+
+// Entropic alpha (Eqs. entropic, H): the non-trivial root of
+//   g(a) = sum_p f_p phi(a x_p) + a L,  x = (f_eq - f)/f,
+//   L = sum_p Delta_p [ln(1 + P_p) - ln(1 + x_p)],  P_p = f_eq_p/(w_p rho) - 1,
+// which equals H(f + a Delta) - H(f) exactly (sum Delta = 0).  g is convex
+// on the positivity interval (0, a_max) with g(0) = 0, g'(0) = L, so a root
+// exists iff L < 0.  Newton from a0; returns the update count in `iters`, or
+// -1 with the fallback min(2, 0.99 a_max) when there is no root or Newton
+// does not converge.
+// f: the node's 19 populations of one component, xs: scratch for x; both
+// are thread-private LDS columns (element p at offset p * BLK), which keeps
+// the p loops rolled and the register footprint small.  rho, u: the FP64
+// moments of f.
+template <typename T>
+__device__ double alpha_solve(const T *f, double *xs, double rho, double ux, double uy, double uz,
+                              double a0, double rtol, int maxit, int &iters) {
+  const double uu = ux * ux + uy * uy + uz * uz;
+  double xmax = 0.0, amax = INFINITY, L = 0.0;
+#pragma unroll 1
+  for (int p = 0; p < NQ; ++p) {
+    const double fp = double(f[p * BLK]);
+    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
+    const double x = d / fp;
+    xs[p * BLK] = x;
+    xmax = fmax(xmax, fabs(x));
+    if (x < 0.0) amax = fmin(amax, -1.0 / x);
+    L += d * (log1p(feq_dev(p, ux, uy, uz, uu)) - log1p(x));
+  }
+  if (xmax < 1e-12) {
+    iters = 0;
+    return 2.0;
+  }
+  double a = a0;
+  if (!(a > 0.0 && a < amax)) a = 0.5 * fmin(amax, 4.0);
+  if (L < 0.0) {
+    for (int it = 0; it <= maxit; ++it) {
+      double S = 0.0, gp = L;
+#pragma unroll 1
+      for (int p = 0; p < NQ; ++p) {
+        const double fp = double(f[p * BLK]);
+        const double x = xs[p * BLK];
+        const double y = a * x;
+        const double l = log1p(y);
+        S += fp * phi_of(y, l);
+        gp += (x * fp) * l;
+      }
+      const double g = S + a * L;
+      if (fabs(g) <= rtol * S) {
+        iters = it;
+        return a;
+      }
+      if (it == maxit) break;
+      double an = (gp > 0.0) ? a - g / gp : 2.0 * a;
+      if (an >= amax) an = 0.5 * (a + amax);
+      if (an <= 0.0) an = 0.5 * a;
+      if (fabs(an - a) <= 4.0 * 2.220446049250313e-16 * a) {
+        iters = it + 1;
+        return an;
+      }
+      a = an;
+    }
+  }
+  iters = -1;
+  return fmin(2.0, 0.99 * amax);
+}
+
+// Matrix 2-norm of a symmetric 3x3 (largest |eigenvalue|), cyclic Jacobi
+// rotations until the off-diagonal part is negligible at the type's precision.
+template <typename R>
+__device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
+  R a[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
+  const R tiny = sizeof(R) == 8 ? R(1e-32) : R(1e-14);
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    const R off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const R diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off <= tiny * diag || off == R(0)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      if (a[p][q] == R(0)) continue;
+      const R th = (a[q][q] - a[p][p]) / (R(2) * a[p][q]);
+      const R t = (th >= R(0) ? R(1) : R(-1)) / (fabs(th) + sqrt(th * th + R(1)));
+      const R c = R(1) / sqrt(t * t + R(1)), s = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const R akp = a[k][p], akq = a[k][q];
+        a[k][p] = c * akp - s * akq;
+        a[k][q] = s * akp + c * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const R apk = a[p][k], aqk = a[q][k];
+        a[p][k] = c * apk - s * aqk;
+        a[q][k] = s * apk + c * aqk;
+      }
+    }
+  }
+  return fmax(fabs(a[0][0]), fmax(fabs(a[1][1]), fabs(a[2][2])));
+}
+
+// Shear rate of Eq. strain2: the root of h(g) = rho (2 nu(g) + c_s^2) g - alpha Pi
+// (Carreau nu, Eq. carreau).  nu0 >= nu >= nu_inf brackets it between the
+// Newtonian roots of the two limits; Newton from the nu0 end, kept inside the
+// bracket (h is strictly increasing for n > 0).
+// Pi = 0 or rho <= 0 (reachable only after negative populations): no
+// positive root, the shear rate is 0 (nu = nu0).
+template <typename R>
+__device__ R shear_rate(R Pn, R rho, R alpha, R nu0, R ninf, R lam, R n) {
+  if (!(Pn > R(0)) || !(rho > R(0))) return R(0);
+  R lo = alpha * Pn / (rho * (R(2) * nu0 + R(CS2)));
+  R hi = alpha * Pn / (rho * (R(2) * ninf + R(CS2)));
+  R g = lo;
+  const R tol = sizeof(R) == 8 ? R(1e-15) : R(2e-7);
+  for (int it = 0; it < 60; ++it) {
+    const R lg = lam * g;
+    const R s = R(1) + lg * lg;
+    const R e = pow(s, R(0.5) * (n - R(3)));  // s^((n-3)/2); s^((n-1)/2) = s * e
+    const R nu = ninf + (nu0 - ninf) * s * e;
+    const R h = rho * (R(2) * nu + R(CS2)) * g - alpha * Pn;
+    if (h > R(0)) hi = g; else lo = g;
+    const R dh = rho * (R(2) * ninf + R(CS2) + R(2) * (nu0 - ninf) * e * (R(1) + n * lg * lg));
+    R gn = g - h / dh;
+    if (!(gn >= lo && gn <= hi)) gn = R(0.5) * (lo + hi);
+    if (fabs(gn - g) <= tol * g || hi - lo <= tol * R(0.1) * hi) return gn;
+    g = gn;
+  }
+  return g;
+}
+
+}  // namespace elbm

@@ -1,0 +1,535 @@
+// elbm_kernels.h -- gfx950 kernels of one time step of the entropic lattice
+// Boltzmann model for charged leaky-dielectric multiphase fluids
+// (Lauricella et al., arXiv:1612.05404).  Every launch covers all boxes of a
+// context: one thread per node, 256-node blocks that never straddle a box.
+//
+// Per step (Sec. II.C):
+//   k_density      pull + component densities rho_s and psi_s = 1 - exp(-rho_s)
+//   k_gradient     19-point gradient of the liquid density
+//   k_interface    curvature K = -div n, theta, charge weights, block partials
+//   k_charge_coef  per-box deterministic reduce -> charge scale and jellium
+//   k_charge_rhs   q and the Poisson right-hand side
+//   k_sor x 2k     red-black SOR half sweeps
+//   (gauge)        zero-mean potential for boxes without Dirichlet nodes
+//   k_efield       |E|^2 with E = E_ext - grad phi
+//   k_collide      pull again, Shan-Chen + electric force, FP64 alpha Newton,
+//                  Carreau beta, exact-difference source, write f*
+#pragma once
+
+#include "elbm_device.h"
+
+namespace elbm {
+
+// Streaming (left side of Eq. lattice-b) by pulling + densities and the
+// Shan-Chen pseudo-potential psi = 1 - exp(-rho) (rho_0 = 1).  Sums run in
+// the field type F in the order p = 0..18.
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live) return;
+  const int k = a.type[nd.g] & 3;
+  int src[NQ];
+  bool bb[NQ];
+  src[0] = nd.n;
+  bb[0] = false;
+#pragma unroll
+  for (int p = 1; p < NQ; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, -kCx[p], -kCy[p], -kCz[p]);
+    bb[p] = (m < 0) || ((a.type[nd.B.off + m] & 3) == K_SOLID);
+    src[p] = m;
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    F r = F(0);
+    if (k == K_INLET || k == K_OUTLET) {
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) r += F(a.fa[(int64_t)(s * NQ + p) * a.N + nd.g]);
+    } else if (k == K_FLUID) {
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) {
+        const T v = bb[p] ? a.fa[(int64_t)(s * NQ + opp(p)) * a.N + nd.g]
+                          : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + src[p]];
+        r += F(v);
+      }
+    }
+    a.rho[(int64_t)s * a.N + nd.g] = r;
+    a.psi[(int64_t)s * a.N + nd.g] = (k == K_SOLID) ? F(0) : -expm1(-r);
+  }
+}
+
+// 19-point isotropic gradient (1/c_s^2) sum_p w_p c_p rho_A(r + c_p); a solid
+// or outside neighbour takes the centre value.
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live) return;
+  F g0 = F(0), g1 = F(0), g2 = F(0);
+  if ((a.type[nd.g] & 3) != K_SOLID) {
+    const F c = a.rho[nd.g];
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+      const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+      F v = c;
+      if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) v = a.rho[nd.B.off + m];
+      g0 += F(wgt(p) * kCx[p]) * v;
+      g1 += F(wgt(p) * kCy[p]) * v;
+      g2 += F(wgt(p) * kCz[p]) * v;
+    }
+    g0 /= F(CS2);
+    g1 /= F(CS2);
+    g2 /= F(CS2);
+  }
+  a.grad[nd.g] = g0;
+  a.grad[a.N + nd.g] = g1;
+  a.grad[2 * a.N + nd.g] = g2;
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ void unit_normal(const Ptrs<T, F> &a, int64_t i, F &n0, F &n1, F &n2) {
+  const F g0 = a.grad[i], g1 = a.grad[a.N + i], g2 = a.grad[2 * a.N + i];
+  const F m = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+  if (m > F(1e-12)) {
+    n0 = g0 / m;
+    n1 = g1 / m;
+    n2 = g2 / m;
+  } else {
+    n0 = n1 = n2 = F(0);
+  }
+}
+
+// Mean curvature K = -div n (n = grad rho_A / |grad rho_A|, Eq.
+// surface-curvature with the sign that makes a convex drop positive),
+// smoothed Heaviside theta, the two charge weights of Eqs. surface-q2 /
+// surface-q3 and their per-block sums (all nodes, Poisson-unknown nodes).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (nd.live) {
+    const uint8_t tt = a.type[nd.g];
+    F bulk = F(0), surf = F(0);
+    if ((tt & 3) != K_SOLID) {
+      F c0, c1, c2;
+      unit_normal(a, nd.g, c0, c1, c2);
+      F div = F(0);
+#pragma unroll
+      for (int p = 1; p < NQ; ++p) {
+        const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+        F n0 = c0, n1 = c1, n2 = c2;
+        if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) unit_normal(a, nd.B.off + m, n0, n1, n2);
+        div += F(wgt(p)) * (F(kCx[p]) * n0 + F(kCy[p]) * n1 + F(kCz[p]) * n2);
+      }
+      const F K = -div / F(CS2);
+      const F rA = a.rho[nd.g];
+      const F theta = F(0.5) * (F(1) + tanh((rA - F(M.rho_th)) / F(M.w_theta)));
+      bulk = rA * theta;
+      const F g0 = a.grad[nd.g], g1 = a.grad[a.N + nd.g], g2 = a.grad[2 * a.N + nd.g];
+      const F gg = g0 * g0 + g1 * g1 + g2 * g2;
+      F wK = F(1);
+      if (M.curvature) wK += sqrt(sqrt(fmax(K, F(0)) / F(M.K_d)));
+      surf = gg * wK;
+    }
+    a.bulk[nd.g] = bulk;
+    a.surf[nd.g] = surf;
+    acc[0] = bulk;
+    acc[1] = surf;
+    if (!(tt & B_DIRICHLET)) {
+      acc[2] = bulk;
+      acc[3] = surf;
+    }
+  }
+  block_sum_store<4>(acc, a.partials + (int64_t)blockIdx.x * 4);
+}
+
+// One block per box: deterministic fixed-order sum of the box's block
+// partials; then the charge scales (conserving: Q/integral, generator: xi)
+// and the neutralising background qbar = sum_unknown q / N_unknown.
+__global__ __launch_bounds__(BLK) void k_charge_coef(const BoxDev *boxes, const double *partials,
+                                                     double *scal, Model M) {
+  const BoxDev B = boxes[blockIdx.x];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < B.nblocks; i += BLK)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += partials[(int64_t)(B.first_block + i) * 4 + k];
+  __shared__ double tot[4];
+  block_sum_store<4>(acc, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double cb, cs;
+    if (M.charge_model == ELBM_CHARGE_CONSERVING) {
+      cb = tot[0] > 0.0 ? B.Q_b / tot[0] : 0.0;
+      cs = tot[1] > 0.0 ? B.Q_s / tot[1] : 0.0;
+    } else {
+      cb = M.xi_b;
+      cs = M.xi_s;
+    }
+    double *o = scal + (int64_t)blockIdx.x * NSCAL;
+    o[0] = cb;
+    o[1] = cs;
+    o[2] = B.n_unknown > 0 ? (cb * tot[2] + cs * tot[3]) / (double)B.n_unknown : 0.0;
+  }
+}
+
+__constant__ int kFace[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+// q and the right-hand side of sum_faces eps_f (phi_nb - phi) =
+// sum_faces eps_f E_ext . e_f - (q - qbar)   (Gauss law with eps = 1 + rho_A).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live) return;
+  const double *sc = a.scal + (int64_t)nd.bb * NSCAL;
+  const uint8_t tt = a.type[nd.g];
+  F q = F(0);
+  if ((tt & 3) != K_SOLID) q = F(sc[0]) * a.bulk[nd.g] + F(sc[1]) * a.surf[nd.g];
+  a.q[nd.g] = q;
+  F r = -(q - F(sc[2]));
+  const F ec = F(1) + a.rho[nd.g];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kFace[f][0], kFace[f][1], kFace[f][2]);
+    if (m < 0) continue;
+    const F ef = F(0.5) * (ec + (F(1) + a.rho[nd.B.off + m]));
+    r += ef * F(nd.B.E[0] * kFace[f][0] + nd.B.E[1] * kFace[f][1] + nd.B.E[2] * kFace[f][2]);
+  }
+  a.rhs[nd.g] = r;
+}
+
+// One red-black SOR half sweep over the nodes of one colour ((x+y+z) & 1).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live) return;
+  if (((nd.x + nd.y + nd.z) & 1) != colour) return;
+  if (a.type[nd.g] & B_DIRICHLET) return;
+  const F ec = F(1) + a.rho[nd.g];
+  F A = F(0), Bs = F(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kFace[f][0], kFace[f][1], kFace[f][2]);
+    if (m < 0) continue;
+    const int64_t gm = nd.B.off + m;
+    const F ef = F(0.5) * (ec + (F(1) + a.rho[gm]));
+    A += ef;
+    Bs += ef * a.phi[gm];
+  }
+  const F om = F(nd.B.omega);
+  a.phi[nd.g] = (F(1) - om) * a.phi[nd.g] + om * (Bs - a.rhs[nd.g]) / A;
+}
+
+// Zero-mean gauge of the potential for boxes without Dirichlet nodes.
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  double acc[1] = {nd.live ? double(a.phi[nd.g]) : 0.0};
+  block_sum_store<1>(acc, a.partials + (int64_t)blockIdx.x * 4);
+}
+
+__global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const double *partials,
+                                                  double *scal) {
+  const BoxDev B = boxes[blockIdx.x];
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < B.nblocks; i += BLK) acc[0] += partials[(int64_t)(B.first_block + i) * 4];
+  __shared__ double tot[1];
+  block_sum_store<1>(acc, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) scal[(int64_t)blockIdx.x * NSCAL + 3] = tot[0] / (double)B.n;
+}
+
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live || nd.B.has_dirichlet) return;
+  a.phi[nd.g] -= F(a.scal[(int64_t)nd.bb * NSCAL + 3]);
+}
+
+// |E|^2 with E = E_ext - grad phi (19-point gradient; an outside neighbour
+// takes the centre value, wall nodes carry their fixed potential).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (!nd.live) return;
+  const F c = a.phi[nd.g];
+  F g0 = F(0), g1 = F(0), g2 = F(0);
+#pragma unroll
+  for (int p = 1; p < NQ; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+    const F v = m >= 0 ? a.phi[nd.B.off + m] : c;
+    g0 += F(wgt(p) * kCx[p]) * v;
+    g1 += F(wgt(p) * kCy[p]) * v;
+    g2 += F(wgt(p) * kCz[p]) * v;
+  }
+  const F e0 = F(nd.B.E[0]) - g0 / F(CS2), e1 = F(nd.B.E[1]) - g1 / F(CS2), e2 = F(nd.B.E[2]) - g2 / F(CS2);
+  a.e2[nd.g] = e0 * e0 + e1 * e1 + e2 * e2;
+}
+
+// The collision (Eq. lattice-b) at fluid nodes with every force term.
+// Forces come first (fields only); then each component in turn: pull its 19
+// populations, FP64 moments, FP64 alpha, viscosity, collision, store.
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int record) {
+  // thread-private LDS columns: populations of the current component and x_p
+  __shared__ T lds_f[NQ * BLK];
+  __shared__ double lds_x[NQ * BLK];
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  unsigned long long c_fb = 0, c_it = 0, c_neg = 0, c_nf = 0, c_col = 0;
+  const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
+  if (nd.live && k == K_FLUID) {
+    // ---- neighbours: local index, solid-or-outside flag
+    int nl[NQ];
+    unsigned solid = 0u;
+    nl[0] = nd.n;
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+      nl[p] = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+      if (nl[p] < 0 || (a.type[nd.B.off + nl[p]] & 3) == K_SOLID) solid |= 1u << p;
+    }
+    // ---- Shan-Chen (Eq. sc) and electric (Eq. force_el2) forces
+    F acc[C][3], wall[3] = {F(0), F(0), F(0)}, gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
+#pragma unroll
+    for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
+    const F phic = a.phi[nd.g], e2c = a.e2[nd.g];
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+      const int m = nl[p];
+      const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
+      if ((solid >> p) & 1u) {
+        wall[0] += F(wgt(p) * kCx[p]);
+        wall[1] += F(wgt(p) * kCy[p]);
+        wall[2] += F(wgt(p) * kCz[p]);
+      } else {
+        F ps[C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) ps[t] = a.psi[(int64_t)t * a.N + gm];
+#pragma unroll
+        for (int s = 0; s < C; ++s) {
+          F sp = F(0);
+#pragma unroll
+          for (int t = 0; t < C; ++t) sp += F(M.G[s][t]) * ps[t];
+          acc[s][0] += F(wgt(p)) * sp * F(kCx[p]);
+          acc[s][1] += F(wgt(p)) * sp * F(kCy[p]);
+          acc[s][2] += F(wgt(p)) * sp * F(kCz[p]);
+        }
+      }
+      const F vp = m >= 0 ? a.phi[gm] : phic;
+      const F ve = m >= 0 ? a.e2[gm] : e2c;
+      gp[0] += F(wgt(p) * kCx[p]) * vp;
+      gp[1] += F(wgt(p) * kCy[p]) * vp;
+      gp[2] += F(wgt(p) * kCz[p]) * vp;
+      ge[0] += F(wgt(p) * kCx[p]) * ve;
+      ge[1] += F(wgt(p) * kCy[p]) * ve;
+      ge[2] += F(wgt(p) * kCz[p]) * ve;
+    }
+    const F qn = a.q[nd.g];
+    const F rA = a.rho[nd.g];
+    F Fel[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const F E = F(nd.B.E[d]) - gp[d] / F(CS2);
+      Fel[d] = qn * E;
+      if (M.electrostriction) Fel[d] += F(0.5) * rA * (ge[d] / F(CS2));
+    }
+    F rt = F(0);
+#pragma unroll
+    for (int s = 0; s < C; ++s) rt += a.rho[(int64_t)s * a.N + nd.g];
+    double mom[3] = {0.0, 0.0, 0.0}, drt = 0.0;
+    T *f = lds_f + threadIdx.x;
+    double *xs = lds_x + threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      // ---- pulled populations and their moments.  The moments are summed
+      // in FP64 whatever the storage: the equilibrium of the alpha solve must
+      // carry exactly the density and momentum of f (sum Delta = 0), or the
+      // rounding of an FP32 sum swamps the O(|Delta|^2) entropy balance.
+      double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) {
+        const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
+        const bool bounce = (p != 0) && ((solid >> q) & 1u);
+        const T v = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g]
+                           : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + nl[q]];
+        f[p * BLK] = v;
+        const double dv = double(v);
+        dr += dv;
+        jx += double(kCx[p]) * dv;
+        jy += double(kCy[p]) * dv;
+        jz += double(kCz[p]) * dv;
+      }
+      drt += dr;
+      const F ps = a.psi[(int64_t)s * a.N + nd.g];
+      const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
+      F Fs[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - F(M.Gw) * ps * ps * wall[d] + frac * Fel[d];
+      mom[0] += jx + 0.5 * double(Fs[0]);
+      mom[1] += jy + 0.5 * double(Fs[1]);
+      mom[2] += jz + 0.5 * double(Fs[2]);
+      // ---- alpha at the component's own velocity (FP64)
+      const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+      const double uu = ux * ux + uy * uy + uz * uz;
+      int its;
+      const double al = alpha_solve<T>(f, xs, dr, ux, uy, uz, 2.0, M.rtol, M.newton_max, its);
+      c_col += 1;
+      if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
+      // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root
+      double nu = M.nu0;
+      if (M.carreau) {
+        double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
+#pragma unroll 1
+        for (int p = 0; p < NQ; ++p) {
+          const double d = double(f[p * BLK]) - feq<double>(p, dr, ux, uy, uz, uu);
+          P00 += d * double(kCx[p] * kCx[p]);
+          P11 += d * double(kCy[p] * kCy[p]);
+          P22 += d * double(kCz[p] * kCz[p]);
+          P01 += d * double(kCx[p] * kCy[p]);
+          P02 += d * double(kCx[p] * kCz[p]);
+          P12 += d * double(kCy[p] * kCz[p]);
+        }
+        const F Pn = sym3_norm2<F>(F(P00), F(P11), F(P22), F(P01), F(P02), F(P12));
+        const F nf = F(nd.B.n_flow);
+        const F gd = shear_rate<F>(Pn, F(dr), F(al), F(M.nu0), F(M.nu_inf), F(M.lam), nf);
+        const F lg = F(M.lam) * gd;
+        nu = double(F(M.nu_inf) + (F(M.nu0) - F(M.nu_inf)) * pow(F(1) + lg * lg, F(0.5) * (nf - F(1))));
+      }
+      const double ab = al * (CS2 / (2.0 * nu + CS2));
+      // ---- exact-difference source (Eq. add) and the update
+      const double vx = ux + double(Fs[0]) / dr, vy = uy + double(Fs[1]) / dr, vz = uz + double(Fs[2]) / dr;
+      const double vv = vx * vx + vy * vy + vz * vz;
+#pragma unroll 1
+      for (int p = 0; p < NQ; ++p) {
+        const double fe = feq<double>(p, dr, ux, uy, uz, uu);
+        const double fe2 = feq<double>(p, dr, vx, vy, vz, vv);
+        const double fp = double(f[p * BLK]);
+        const double v = fp + ab * (fe - fp) + (fe2 - fe);
+        const T tv = T(v);
+        if (!isfinite(tv)) c_nf += 1;
+        else if (tv < T(0)) c_neg += 1;
+        a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = tv;
+      }
+      if (record) {
+        a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
+        a.rec_iters[(int64_t)s * a.N + nd.g] = its;
+      }
+    }
+    if (record) {
+      a.rec_u[nd.g] = F(mom[0] / drt);
+      a.rec_u[a.N + nd.g] = F(mom[1] / drt);
+      a.rec_u[2 * a.N + nd.g] = F(mom[2] / drt);
+    }
+  } else if (nd.live && record) {
+    // boundary and wall nodes: populations stay; recorded velocity sum j / sum rho
+    double r = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    if (k != K_SOLID) {
+#pragma unroll
+      for (int s = 0; s < C; ++s)
+#pragma unroll
+        for (int p = 0; p < NQ; ++p) {
+          const double v = double(a.fa[(int64_t)(s * NQ + p) * a.N + nd.g]);
+          r += v;
+          m0 += double(kCx[p]) * v;
+          m1 += double(kCy[p]) * v;
+          m2 += double(kCz[p]) * v;
+        }
+    }
+    a.rec_u[nd.g] = r > 0.0 ? F(m0 / r) : F(0);
+    a.rec_u[a.N + nd.g] = r > 0.0 ? F(m1 / r) : F(0);
+    a.rec_u[2 * a.N + nd.g] = r > 0.0 ? F(m2 / r) : F(0);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
+      a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
+    }
+  }
+  // ---- counters: wave sums, one atomic per wave and counter
+  c_fb = wave_sum_u64(c_fb);
+  c_it = wave_sum_u64(c_it);
+  c_neg = wave_sum_u64(c_neg);
+  c_nf = wave_sum_u64(c_nf);
+  c_col = wave_sum_u64(c_col);
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
+    if (c_fb) atomicAdd(cn + 0, c_fb);
+    if (c_it) atomicAdd(cn + 1, c_it);
+    if (c_neg) atomicAdd(cn + 2, c_neg);
+    if (c_nf) {
+      atomicAdd(cn + 3, c_nf);
+      atomicOr(a.err, 1u);
+    }
+    if (c_col) atomicAdd(cn + 4, c_col);
+  }
+}
+
+// ------------------------------------------------------ init / transfer
+// Initial populations of direction p of component s for one box.  Staged
+// host planes are `ps` doubles apart (the largest box size).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_init_dir(Ptrs<T, F> a, Model M, int box, int s, int p,
+                                                  const double *rho0, const double *u0,
+                                                  const double *ubc, const double *xi, double amp,
+                                                  int64_t ps) {
+  const BoxDev B = a.boxes[box];
+  const int n = blockIdx.x * BLK + threadIdx.x;
+  if (n >= B.n) return;
+  const int64_t g = B.off + n;
+  const int k = a.type[g] & 3;
+  double v = 0.0;
+  if (k == K_FLUID) {
+    const double ux = u0[n], uy = u0[ps + n], uz = u0[2 * ps + n];
+    v = feq<double>(p, rho0[s * ps + n], ux, uy, uz, ux * ux + uy * uy + uz * uz);
+    if (xi) v = v * (1.0 + amp * xi[n]);
+  } else if (k == K_INLET) {
+    const double ux = ubc ? ubc[n] : 0.0, uy = ubc ? ubc[ps + n] : 0.0, uz = ubc ? ubc[2 * ps + n] : 0.0;
+    v = feq<double>(p, M.rho_in[s], ux, uy, uz, ux * ux + uy * uy + uz * uz);
+  } else if (k == K_OUTLET) {
+    v = feq<double>(p, M.rho_out[s], 0.0, 0.0, 0.0, 0.0);
+  }
+  a.fa[(int64_t)(s * NQ + p) * a.N + g] = T(v);
+  a.fb[(int64_t)(s * NQ + p) * a.N + g] = T(v);
+}
+
+template <typename X>
+__global__ __launch_bounds__(BLK) void k_to_double(const X *src, double *dst, int n) {
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) dst[i] = double(src[i]);
+}
+template <typename X>
+__global__ __launch_bounds__(BLK) void k_from_double(const double *src, X *dst, X *dst2, int n) {
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) {
+    dst[i] = X(src[i]);
+    if (dst2) dst2[i] = X(src[i]);
+  }
+}
+
+// Mass and momentum partial sums of one box's current populations.
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK) void k_diag(Ptrs<T, F> a, int box, double *out) {
+  const BoxDev B = a.boxes[box];
+  const int n = blockIdx.x * BLK + threadIdx.x;
+  double v5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (n < B.n) {
+    const int64_t g = B.off + n;
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) {
+        const double v = double(a.fa[(int64_t)(s * NQ + p) * a.N + g]);
+        v5[s] += v;
+        v5[2] += kCx[p] * v;
+        v5[3] += kCy[p] * v;
+        v5[4] += kCz[p] * v;
+      }
+  }
+  block_sum_store<5>(v5, out + (int64_t)blockIdx.x * 5);
+}
+
+}  // namespace elbm

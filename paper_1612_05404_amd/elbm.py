@@ -17,7 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelbm.so")
 
 ELBM_OK, ELBM_EINVAL, ELBM_ENOMEM, ELBM_EHIP, ELBM_ENONFINITE, ELBM_ESTATE = 0, -1, -2, -3, -4, -7
-STORAGE_F64, STORAGE_F32 = 0, 1
+STORAGE_F64, STORAGE_F32, STORAGE_F32_ALL = 0, 1, 2
+# dtype names: "f64" all FP64; "f32" FP32 populations + FP64 fields; "f32all" all FP32
+STORAGE = {"f64": STORAGE_F64, "f32": STORAGE_F32, "f32all": STORAGE_F32_ALL}
 Q = 19
 
 
@@ -147,7 +149,9 @@ class Lattice:
     """Boxes of one parameter set advanced by the HIP library on one GPU.
 
     ``params`` is an inputs.Params, ``boxes`` a list of inputs.Box,
-    ``dtype`` "f64" or "f32" (population and field storage)."""
+    ``dtype`` "f64" (FP64 populations and fields), "f32" (FP32 populations,
+    FP64 fields) or "f32all" (FP32 populations and fields); the entropic
+    alpha is FP64 in every mode."""
 
     def __init__(self, params, boxes: Sequence, dtype: str = "f64", device: str = "cuda:0",
                  stream=None):
@@ -156,7 +160,9 @@ class Lattice:
         self.params = params
         self.boxes = list(boxes)
         self.C = params.ncomp
-        storage = STORAGE_F64 if dtype == "f64" else STORAGE_F32
+        if dtype not in STORAGE:
+            raise ValueError(f"dtype must be one of {sorted(STORAGE)}")
+        storage = STORAGE[dtype]
         self._P = make_params(params, storage)
         self._B = (elbm_box * len(self.boxes))(*[make_box(params, b) for b in self.boxes])
         h = ct.c_void_p()

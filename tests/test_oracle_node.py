@@ -192,3 +192,11 @@ def test_shear_rate_newtonian_closed_form(ora):
     got = ora.shear_rate(Pn, rho, alpha, nu0, 0.05, 10.0, 1.0)
     assert math.isclose(got, alpha * Pn / (rho * (2 * nu0 + CS2)), rel_tol=1e-14)
     assert ora.shear_rate(0.0, rho, alpha, nu0, 0.05, 10.0, 0.5) == 0.0
+
+
+def test_shear_rate_degenerate_inputs(ora):
+    # No stress, or a non-positive density (only after negative populations):
+    # Eq. strain2 has no positive root and the shear rate is taken as zero.
+    assert ora.shear_rate(0.0, 1.0, 2.0, 0.5, 0.05, 10.0, 0.5) == 0.0
+    assert ora.shear_rate(1e-3, 0.0, 2.0, 0.5, 0.05, 10.0, 0.5) == 0.0
+    assert ora.shear_rate(1e-3, -1e-3, 2.0, 0.5, 0.05, 10.0, 0.5) == 0.0
