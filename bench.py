@@ -69,6 +69,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--alpha-guess", default="series", choices=["series", "standard"],
+                    help="initial guess of the alpha Newton iteration for the reported value")
+    ap.add_argument("--single-mode", action="store_true",
+                    help="time only the reported guess (no comparison run)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -82,31 +86,47 @@ def main():
     wl = inputs.WORKLOADS[args.workload]()
     box = wl.boxes[0]
     nodes = wl.nodes
-    print(f"[bench] workload {wl.name} {box.nx}x{box.ny}x{box.nz} dtype {wl.dtype} "
-          f"sor_sweeps {wl.params.sor_sweeps}", file=sys.stderr, flush=True)
-    lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0")
-    lat.step(args.warmup, record=False)
-    lat.sync()
-    lat.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.step(args.steps, record=False)
-    lat.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ph = lat.timing()
-    lat.set_timing(False)
-    # one recorded step for the solver statistics (outside the timed region)
-    lat.step(1, record=True)
-    diag = lat.diagnostics(0)
-    dt = t1 - t0
-    mlups = nodes * args.steps / dt / 1e6
     esz = 8 if wl.dtype == "f64" else 4
+    modes = [args.alpha_guess] + [m for m in ("standard", "series") if m != args.alpha_guess]
+    results = {}
+    for mode in modes:
+        print(f"[bench] workload {wl.name} {box.nx}x{box.ny}x{box.nz} dtype {wl.dtype} sor_sweeps "
+              f"{wl.params.sor_sweeps} alpha guess {mode}", file=sys.stderr, flush=True)
+        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
+        lat.step(args.warmup, record=False)
+        lat.sync()
+        lat.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(args.steps, record=False)
+        lat.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ph = lat.timing()
+        lat.set_timing(False)
+        # one recorded step for the solver statistics (outside the timed region)
+        lat.step(1, record=True)
+        diag = lat.diagnostics(0)
+        results[mode] = dict(dt=t1 - t0, ph=ph, diag=diag)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        if args.single_mode:
+            break
+    r = results[args.alpha_guess]
+    dt, ph, diag = r["dt"], r["ph"], r["diag"]
+    mlups = nodes * args.steps / dt / 1e6
     steps_timed = max(ph["steps"], 1)
     coll_ms = ph["collide"] / steps_timed
     cb = collide_bytes_per_node(esz, wl.params.ncomp)
     achieved = cb * nodes / (coll_ms * 1e-3) / 1e9
     sb = step_bytes_per_node(esz, wl.params.ncomp, wl.params.sor_sweeps)
+    comparison = {
+        m: {"mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
+            "collide_ms": round(v["ph"]["collide"] / max(v["ph"]["steps"], 1), 5),
+            "mean_newton_iters": round(v["diag"]["mean_newton_iters"], 4)}
+        for m, v in results.items()
+    }
     out = {
         "metric": METRIC,
         "value": round(mlups, 3),
@@ -126,7 +146,7 @@ def main():
             if wl.name == "efield_drop" else f"{wl.name}: {box.nx}x{box.ny}x{box.nz}",
             "nodes": nodes,
             "sor_sweeps": wl.params.sor_sweeps,
-            "alpha_guess": "Newton from alpha=2",
+            "alpha_guess": args.alpha_guess,
             "alpha_precision": "f64",
         },
         "roofline": {
@@ -145,6 +165,7 @@ def main():
         "phase_ms_per_step": {k: round(v / steps_timed, 5) for k, v in ph.items() if k != "steps"},
         "mean_newton_iters": round(diag["mean_newton_iters"], 4),
         "alpha_fallback_frac": round(diag["n_fallback"] / max(diag["n_collisions"], 1), 6),
+        "alpha_guess_comparison": comparison,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -61,7 +61,12 @@ typedef enum {
  * are FP64 in every mode. */
 enum { ELBM_STORAGE_F64 = 0, ELBM_STORAGE_F32 = 1, ELBM_STORAGE_F32_ALL = 2 };
 enum { ELBM_CHARGE_CONSERVING = 0, ELBM_CHARGE_GENERATOR = 1 };
-enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1 };
+/* Initial guess of the alpha Newton iteration; every guess is polished to the
+ * same stopping rule.  STANDARD: alpha0 = 2 (the BGK value).  SERIES: root of
+ * the degree-7 truncation of the entropy balance in powers of alpha (no
+ * logarithms), used where that truncation is accurate.  MLP: the learned
+ * starter. */
+enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1, ELBM_GUESS_SERIES = 2 };
 
 /* Model constants shared by every box of a context. */
 typedef struct {

@@ -150,13 +150,6 @@ void ora_feq(double rho, const double u[3], double out[Q]) {
     }
 }
 
-/* f_eq / (w rho) - 1, written without cancellation. */
-static double feq_dev(int p, const double u[3]) {
-    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    double cu = CV[p][0] * u[0] + CV[p][1] * u[1] + CV[p][2] * u[2];
-    return cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
-}
-
 /* phi(y) = (1+y) ln(1+y) - y, accurate for small |y| (its Taylor series
  * sum_{k>=2} (-1)^k y^k / (k(k-1)) summed to convergence). */
 static double phi_fn(double y) {
@@ -180,9 +173,9 @@ static double phi_fn(double y) {
  * root of H(f + alpha (f_eq - f)) = H(f), H(f) = sum_p f_p ln(f_p / w_p).
  * With Delta = f_eq - f and x_p = Delta_p / f_p the difference is, exactly,
  *   g(alpha) = sum_p f_p phi(alpha x_p) + alpha L,
- *   L = sum_p Delta_p ln(f_p / (w_p rho))
- *     = sum_p Delta_p [ln(1 + P_p) - ln(1 + x_p)],  P_p = f_eq_p/(w_p rho) - 1,
- * using sum_p Delta_p = 0 (f and f_eq carry the same density).
+ *   L = sum_p Delta_p ln(f_p / (w_p rho)),
+ * using sum_p Delta_p = 0 (f and f_eq carry the same density).  A
+ * non-positive population leaves H(f) undefined: fallback.
  * g is convex on the positivity interval 0 < alpha < alpha_max, g(0) = 0,
  * g'(0) = L, so a root exists iff L < 0 and it is unique.
  * Newton from alpha0 (2 = the BGK limit, or a supplied guess); a step that
@@ -195,16 +188,24 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
                  double alpha0, double rtol, int maxit, int *iters_out) {
     double D[Q], x[Q];
     double xmax = 0.0, amax = INFINITY;
+    int nonpos = 0;
     for (int p = 0; p < Q; ++p) {
         D[p] = feq[p] - f[p];
         x[p] = D[p] / f[p];
+        if (!(f[p] > 0.0)) nonpos = 1;
         if (fabs(x[p]) > xmax) xmax = fabs(x[p]);
         if (x[p] < 0.0 && -1.0 / x[p] < amax) amax = -1.0 / x[p];
     }
+    if (nonpos) {  /* H(f) is undefined for a non-positive population */
+        *iters_out = -1;
+        return fmin(2.0, 0.99 * amax);
+    }
     if (xmax < 1e-12) { *iters_out = 0; return 2.0; }
+    /* L = sum_p Delta_p ln(f_p / (w_p rho)): defined for every f > 0, also
+     * where the polynomial equilibrium is negative */
     double L = 0.0;
-    for (int p = 0; p < Q; ++p) L += D[p] * (log1p(feq_dev(p, u)) - log1p(x[p]));
-    (void)rho;
+    for (int p = 0; p < Q; ++p) L += D[p] * log1p((f[p] - WV[p] * rho) / (WV[p] * rho));
+    (void)u;
     double a = alpha0;
     if (!(a > 0.0 && a < amax)) a = 0.5 * (amax < 4.0 ? amax : 4.0);
     if (L < 0.0) {

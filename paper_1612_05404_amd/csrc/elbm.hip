@@ -84,6 +84,7 @@ Model make_model(const elbm_params &P) {
   M.electrostriction = P.electrostriction;
   M.charge_model = P.charge_model;
   M.newton_max = P.newton_max;
+  M.alpha_guess = P.alpha_guess;
   for (int s = 0; s < 2; ++s)
     for (int t = 0; t < 2; ++t) M.G[s][t] = P.G[s][t];
   M.Gw = P.Gw;
@@ -331,7 +332,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   if (P->charge_model != ELBM_CHARGE_CONSERVING && P->charge_model != ELBM_CHARGE_GENERATOR) return ELBM_EINVAL;
   if (!(P->w_theta > 0.0) || !(P->K_d > 0.0) || !(P->nu0 > 0.0) || !(P->newton_rtol > 0.0)) return ELBM_EINVAL;
   if (P->carreau && !(P->nu_inf > 0.0 && P->lam >= 0.0)) return ELBM_EINVAL;
-  if (P->alpha_guess != ELBM_GUESS_STANDARD) return ELBM_EINVAL;
+  if (P->alpha_guess != ELBM_GUESS_STANDARD && P->alpha_guess != ELBM_GUESS_SERIES) return ELBM_EINVAL;
   elbm_ctx *c = new (std::nothrow) elbm_ctx();
   if (!c) return ELBM_ENOMEM;
   c->P = *P;

@@ -39,7 +39,7 @@ struct BoxDev {
 };
 
 struct Model {
-  int32_t C, carreau, curvature, electrostriction, charge_model, newton_max;
+  int32_t C, carreau, curvature, electrostriction, charge_model, newton_max, alpha_guess, pad;
   double G[2][2], Gw, nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
   double rho_in[2], rho_out[2];
 };
@@ -138,16 +138,53 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // -------------------------------------------------------- equilibrium
-// Second-order equilibrium (Sec. II, below Eq. lattice-b).
+// Second-order equilibrium (Sec. II, below Eq. lattice-b), with the exact
+// lattice factors 1/c_s^2 = 3 and 1/(2 c_s^4) = 4.5 (no divisions):
+// w rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u].
 template <typename R>
 __device__ __forceinline__ R feq(int p, R rho, R ux, R uy, R uz, R uu) {
   const R cu = R(kCx[p]) * ux + R(kCy[p]) * uy + R(kCz[p]) * uz;
-  return R(wgt(p)) * rho * (R(1) + cu / R(CS2) + (cu * cu - R(CS2) * uu) / (R(2) * R(CS2) * R(CS2)));
+  return R(wgt(p)) * rho * (R(1) + R(3) * cu + R(4.5) * (cu * cu) - R(1.5) * uu);
 }
-// f_eq / (w rho) - 1 without cancellation
-__device__ __forceinline__ double feq_dev(int p, double ux, double uy, double uz, double uu) {
-  const double cu = double(kCx[p]) * ux + double(kCy[p]) * uy + double(kCz[p]) * uz;
-  return cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
+
+// 1/d to ~1 ulp: hardware reciprocal estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return fma(fma(-d, r, 1.0), r, r);
+}
+
+// ln(1 + y) for y > -1 to ~2 ulp (the libm version carries double-double
+// internals and is ~5x longer).  t = 1 + y with its exact rounding error c
+// (TwoSum); t = m 2^e with m in [1/sqrt2, sqrt2); ln m = 2 atanh(s),
+// s = (m-1)/(m+1), |s| <= 0.1716, summed as 2 s sum_{k=0}^{10} s^2k/(2k+1)
+// (first dropped term 2e-17 relative); ln(1+y) = e ln2 + ln m + c/t.
+__device__ __forceinline__ double log1p_fast(double y) {
+  const double t = 1.0 + y;
+  const double bv = t - 1.0, av = t - bv;
+  const double c = (1.0 - av) + (y - bv);
+  double m = __builtin_amdgcn_frexp_mant(t);
+  int e = __builtin_amdgcn_frexp_exp(t);
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) * rcp_nr(m + 1.0);
+  const double s2 = s * s;
+  double q = 1.0 / 21.0;
+  q = fma(q, s2, 1.0 / 19.0);
+  q = fma(q, s2, 1.0 / 17.0);
+  q = fma(q, s2, 1.0 / 15.0);
+  q = fma(q, s2, 1.0 / 13.0);
+  q = fma(q, s2, 1.0 / 11.0);
+  q = fma(q, s2, 1.0 / 9.0);
+  q = fma(q, s2, 1.0 / 7.0);
+  q = fma(q, s2, 1.0 / 5.0);
+  q = fma(q, s2, 1.0 / 3.0);
+  q = fma(q, s2, 1.0);
+  const double de = double(e);
+  // ln2 split: the high part has 33 significant bits, so de * LN2_HI is exact
+  return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * q + c * __builtin_amdgcn_rcp(t)));
 }
 
 // phi(y) = (1+y) ln(1+y) - y given l = ln(1+y), cancellation-free: Taylor
@@ -175,47 +212,83 @@ __device__ __forceinline__ double phi_of(double y, double l) {
 }
 
 // Entropic alpha (Eqs. entropic, H): the non-trivial root of
-//   g(a) = sum_p f_p phi(a x_p) + a L,  x = (f_eq - f)/f,
-//   L = sum_p Delta_p [ln(1 + P_p) - ln(1 + x_p)],  P_p = f_eq_p/(w_p rho) - 1,
-// which equals H(f + a Delta) - H(f) exactly (sum Delta = 0).  g is convex
-// on the positivity interval (0, a_max) with g(0) = 0, g'(0) = L, so a root
-// exists iff L < 0.  Newton from a0; returns the update count in `iters`, or
-// -1 with the fallback min(2, 0.99 a_max) when there is no root or Newton
-// does not converge.
-// f: the node's 19 populations of one component, xs: scratch for x; both
-// are thread-private LDS columns (element p at offset p * BLK), which keeps
-// the p loops rolled and the register footprint small.  rho, u: the FP64
-// moments of f.
+//   g(a) = sum_p f_p phi(a x_p) + a L,  x = (f_eq - f)/f,  L = sum_p Delta_p ln(f_p / (w_p rho)),
+// which equals H(f + a Delta) - H(f) exactly (sum Delta = 0).  L is formed
+// as sum_p Delta_p log1p((f_p - w_p rho)/(w_p rho)) (one log per direction,
+// no cancellation).  g is convex on the positivity interval (0, a_max) with
+// g(0) = 0, g'(0) = L, so a root exists iff L < 0.
+// Newton from a0 = 2, or from the series starter when `series` is set: the
+// root of the degree-7 truncation of g(a)/a = L + sum_k (-1)^k a^(k-1) M_k /
+// (k(k-1)), M_k = sum_p f_p x_p^k, accepted when a0 max|x| < 0.2 (truncation
+// below 1e-8 relative).  Either way the result is polished to the same
+// stopping rule.  Returns the update count in `iters`, or -1 with the
+// fallback min(2, 0.99 a_max) when there is no root, Newton does not
+// converge, or a population is not positive (H undefined).
+// f: the node's 19 populations of one component, xs: scratch for x; both are
+// thread-private LDS columns (element p at offset p * BLK), which keeps the
+// p loops rolled and the register footprint small.  rho, u: FP64 moments of f.
 template <typename T>
 __device__ double alpha_solve(const T *f, double *xs, double rho, double ux, double uy, double uz,
-                              double a0, double rtol, int maxit, int &iters) {
+                              bool series, double rtol, int maxit, int &iters) {
   const double uu = ux * ux + uy * uy + uz * uz;
+  const double irho = rcp_nr(rho);
   double xmax = 0.0, amax = INFINITY, L = 0.0;
-#pragma unroll 1
+  double M2 = 0.0, M3 = 0.0, M4 = 0.0, M5 = 0.0, M6 = 0.0, M7 = 0.0;
+  bool nonpos = false;
+#pragma unroll 4
   for (int p = 0; p < NQ; ++p) {
     const double fp = double(f[p * BLK]);
+    const double wr = wgt(p) * rho;
     const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
-    const double x = d / fp;
+    const double x = d * rcp_nr(fp);
+    nonpos |= !(fp > 0.0);
     xs[p * BLK] = x;
     xmax = fmax(xmax, fabs(x));
-    if (x < 0.0) amax = fmin(amax, -1.0 / x);
-    L += d * (log1p(feq_dev(p, ux, uy, uz, uu)) - log1p(x));
+    if (x < 0.0) amax = fmin(amax, -rcp_nr(x));
+    L += d * log1p_fast((fp - wr) * (irho * (1.0 / wgt(p))));
+    double t = fp * x * x;
+    M2 += t;
+    t *= x;
+    M3 += t;
+    t *= x;
+    M4 += t;
+    t *= x;
+    M5 += t;
+    t *= x;
+    M6 += t;
+    M7 += t * x;
+  }
+  if (nonpos) {  // H(f) is undefined for a non-positive population
+    iters = -1;
+    return fmin(2.0, 0.99 * amax);
   }
   if (xmax < 1e-12) {
     iters = 0;
     return 2.0;
   }
-  double a = a0;
+  double a = 2.0;
+  if (series && L < 0.0) {
+    // Newton on the truncated series from 2 (no logarithms)
+    double b = 2.0;
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {
+      const double q = L + b * (M2 / 2.0 + b * (-M3 / 6.0 + b * (M4 / 12.0 + b * (-M5 / 20.0 + b * (M6 / 30.0 - b * M7 / 42.0)))));
+      const double dq = M2 / 2.0 + b * (-M3 / 3.0 + b * (M4 / 4.0 + b * (-M5 / 5.0 + b * (M6 / 6.0 - b * M7 / 7.0))));
+      if (!(dq > 0.0)) break;
+      b -= q / dq;
+    }
+    if (b > 0.0 && b < amax && b * xmax < 0.2) a = b;
+  }
   if (!(a > 0.0 && a < amax)) a = 0.5 * fmin(amax, 4.0);
   if (L < 0.0) {
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L;
-#pragma unroll 1
+#pragma unroll 4
       for (int p = 0; p < NQ; ++p) {
         const double fp = double(f[p * BLK]);
         const double x = xs[p * BLK];
         const double y = a * x;
-        const double l = log1p(y);
+        const double l = log1p_fast(y);
         S += fp * phi_of(y, l);
         gp += (x * fp) * l;
       }

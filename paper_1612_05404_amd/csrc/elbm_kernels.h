@@ -377,10 +377,13 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
       const double uu = ux * ux + uy * uy + uz * uz;
       int its;
-      const double al = alpha_solve<T>(f, xs, dr, ux, uy, uz, 2.0, M.rtol, M.newton_max, its);
+      const double al = alpha_solve<T>(f, xs, dr, ux, uy, uz, M.alpha_guess == ELBM_GUESS_SERIES, M.rtol,
+                                       M.newton_max, its);
       c_col += 1;
       if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
-      // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root
+      // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root,
+      // evaluated in the field precision
+      using R = F;
       double nu = M.nu0;
       if (M.carreau) {
         double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
@@ -394,22 +397,26 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
           P02 += d * double(kCx[p] * kCz[p]);
           P12 += d * double(kCy[p] * kCz[p]);
         }
-        const F Pn = sym3_norm2<F>(F(P00), F(P11), F(P22), F(P01), F(P02), F(P12));
-        const F nf = F(nd.B.n_flow);
-        const F gd = shear_rate<F>(Pn, F(dr), F(al), F(M.nu0), F(M.nu_inf), F(M.lam), nf);
-        const F lg = F(M.lam) * gd;
-        nu = double(F(M.nu_inf) + (F(M.nu0) - F(M.nu_inf)) * pow(F(1) + lg * lg, F(0.5) * (nf - F(1))));
+        const R Pn = sym3_norm2<R>(R(P00), R(P11), R(P22), R(P01), R(P02), R(P12));
+        const R nf = R(nd.B.n_flow);
+        const R gd = shear_rate<R>(Pn, R(dr), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
+        const R lg = R(M.lam) * gd;
+        nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow(R(1) + lg * lg, R(0.5) * (nf - R(1))));
       }
       const double ab = al * (CS2 / (2.0 * nu + CS2));
-      // ---- exact-difference source (Eq. add) and the update
-      const double vx = ux + double(Fs[0]) / dr, vy = uy + double(Fs[1]) / dr, vz = uz + double(Fs[2]) / dr;
-      const double vv = vx * vx + vy * vy + vz * vz;
+      // ---- exact-difference source (Eq. add): with v = u + F/rho,
+      // f_eq(v) - f_eq(u) = w rho [3 c.du + 4.5 (c.du)(c.(u+v)) - 1.5 du.(u+v)]
+      const double dx_ = double(Fs[0]) / dr, dy_ = double(Fs[1]) / dr, dz_ = double(Fs[2]) / dr;
+      const double sx = 2.0 * ux + dx_, sy = 2.0 * uy + dy_, sz = 2.0 * uz + dz_;
+      const double ds = dx_ * sx + dy_ * sy + dz_ * sz;
 #pragma unroll 1
       for (int p = 0; p < NQ; ++p) {
         const double fe = feq<double>(p, dr, ux, uy, uz, uu);
-        const double fe2 = feq<double>(p, dr, vx, vy, vz, vv);
+        const double cd = double(kCx[p]) * dx_ + double(kCy[p]) * dy_ + double(kCz[p]) * dz_;
+        const double cs = double(kCx[p]) * sx + double(kCy[p]) * sy + double(kCz[p]) * sz;
+        const double src = wgt(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
         const double fp = double(f[p * BLK]);
-        const double v = fp + ab * (fe - fp) + (fe2 - fe);
+        const double v = fp + ab * (fe - fp) + src;
         const T tv = T(v);
         if (!isfinite(tv)) c_nf += 1;
         else if (tv < T(0)) c_neg += 1;

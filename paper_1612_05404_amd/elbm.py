@@ -20,6 +20,8 @@ ELBM_OK, ELBM_EINVAL, ELBM_ENOMEM, ELBM_EHIP, ELBM_ENONFINITE, ELBM_ESTATE = 0, 
 STORAGE_F64, STORAGE_F32, STORAGE_F32_ALL = 0, 1, 2
 # dtype names: "f64" all FP64; "f32" FP32 populations + FP64 fields; "f32all" all FP32
 STORAGE = {"f64": STORAGE_F64, "f32": STORAGE_F32, "f32all": STORAGE_F32_ALL}
+# initial guess of the alpha Newton iteration (every guess is polished to the same rule)
+GUESS = {"standard": 0, "mlp": 1, "series": 2}
 Q = 19
 
 
@@ -109,12 +111,12 @@ def load(path: str = LIB_PATH):
     return L
 
 
-def make_params(p, storage: int) -> elbm_params:
+def make_params(p, storage: int, guess: int = 0) -> elbm_params:
     P = elbm_params()
     P.ncomp, P.storage = int(p.ncomp), int(storage)
     P.carreau, P.curvature, P.electrostriction = int(p.carreau), int(p.curvature), int(p.electrostriction)
     P.charge_model, P.sor_sweeps, P.newton_max = int(p.charge_model), int(p.sor_sweeps), int(p.newton_max)
-    P.alpha_guess = 0
+    P.alpha_guess = int(guess)
     for s in range(2):
         for t in range(2):
             P.G[s][t] = float(p.G[s][t]) if s < len(p.G) and t < len(p.G[s]) else 0.0
@@ -154,7 +156,7 @@ class Lattice:
     alpha is FP64 in every mode."""
 
     def __init__(self, params, boxes: Sequence, dtype: str = "f64", device: str = "cuda:0",
-                 stream=None):
+                 stream=None, alpha_guess: str = "standard"):
         import torch
         self.L = load()
         self.params = params
@@ -163,7 +165,9 @@ class Lattice:
         if dtype not in STORAGE:
             raise ValueError(f"dtype must be one of {sorted(STORAGE)}")
         storage = STORAGE[dtype]
-        self._P = make_params(params, storage)
+        if alpha_guess not in GUESS:
+            raise ValueError(f"alpha_guess must be one of {sorted(GUESS)}")
+        self._P = make_params(params, storage, GUESS[alpha_guess])
         self._B = (elbm_box * len(self.boxes))(*[make_box(params, b) for b in self.boxes])
         h = ct.c_void_p()
         self._check(self.L.elbm_create(ct.byref(self._P), self._B, len(self.boxes), ct.byref(h)), None)

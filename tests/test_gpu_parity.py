@@ -88,6 +88,31 @@ def test_drop32_fp64_parity_100_steps(elbm):
     _say(f"    diag {d}")
 
 
+def test_series_starter_same_alpha_fewer_iterations(elbm):
+    # The series starter changes only where Newton starts: fields match the
+    # oracle at the FP64 bar, alpha matches the plain solver's, and the mean
+    # number of Newton updates drops.
+    import oracle as ora
+    wl = inputs.drop32()
+    _say("[gpu parity] drop32 with the series starter: f64, 100 steps")
+    plain = elbm.Lattice(wl.params, wl.boxes, "f64")
+    ser = elbm.Lattice(wl.params, wl.boxes, "f64", alpha_guess="series")
+    plain.step(100, record=True)
+    ser.step(100, record=True)
+    o = ora.Oracle(wl.params, wl.boxes[0], nthreads=NTHREADS)
+    o.step(100)
+    compare(ser, 0, o, 1e-12)
+    a0, i0 = plain.read_alpha(0)
+    a1, i1 = ser.read_alpha(0)
+    both = (i0 >= 0) & (i1 >= 0)
+    err = np.abs(a1 - a0)[both] / a0[both]
+    d0, d1 = plain.diagnostics(0), ser.diagnostics(0)
+    _say(f"    alpha series vs plain: q0.999 rel {np.quantile(err, 0.999):.2e} max {err.max():.2e}; mean Newton "
+         f"updates plain {d0['mean_newton_iters']:.3f} series {d1['mean_newton_iters']:.3f}")
+    assert np.quantile(err, 0.999) < 1e-9
+    assert d1["mean_newton_iters"] < 0.8 * d0["mean_newton_iters"]
+
+
 def test_ragged_multibox_all_terms_fp64(elbm):
     # Several boxes in one launch, sizes that are not multiples of the block,
     # every term on: surface charge with curvature, external field, Carreau.

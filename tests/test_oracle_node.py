@@ -98,6 +98,48 @@ def test_alpha_vs_decimal_bisection(ora, seed, jit, umax):
     assert abs(a - ref) <= 1e-11 * ref, (a, ref)
 
 
+def test_alpha_where_polynomial_equilibrium_is_negative(ora):
+    # A fast node: some f_eq_p < 0 while every f_p > 0.  H(f + alpha Delta) is
+    # still defined on the positivity interval and the root must be the literal one.
+    c, w = ora.lattice()
+    rng = np.random.default_rng(6)
+    fac = rng.uniform(5, 40)
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    f = w * (1.0 + 0.5 * rng.uniform(-1, 1, 19)) * np.exp(fac / 10 * (c @ d))  # strong drift along d
+    r = f.sum()
+    u = (c.T @ f) / r
+    fe = ora.feq(r, u)
+    assert fe.min() < 0 < f.min()
+    a, it = ora.alpha(f, fe, u, r)
+    assert it >= 0
+    x = (fe - f) / f
+    amax = np.min(-1 / x[x < 0])
+    # bracket the non-trivial root on a grid of the positivity interval, then bisect
+    grid = np.linspace(1e-3, amax * (1 - 1e-9), 400)
+    getcontext().prec = 60
+    F = [Decimal(float(v)) for v in f]
+    E = [Decimal(float(v)) for v in fe]
+    W = [Decimal(1) / Decimal(3)] + [Decimal(1) / Decimal(18)] * 6 + [Decimal(1) / Decimal(36)] * 12
+    H0 = _H_dec(F, W)
+    g = [float(_H_dec([fi + Decimal(float(t)) * (ei - fi) for fi, ei in zip(F, E)], W) - H0) for t in grid]
+    k = next(i for i in range(len(g) - 1) if g[i] < 0 <= g[i + 1])
+    ref = _alpha_decimal(f, fe, w, grid[k], grid[k + 1])
+    assert abs(a - ref) <= 1e-11 * ref, (a, ref)
+
+
+def test_alpha_nonpositive_population_falls_back(ora):
+    # H(f) needs f > 0: a non-positive population gives the fallback value.
+    c, w = ora.lattice()
+    u = np.zeros(3)
+    fe = ora.feq(1.0, u)
+    f = fe.copy()
+    f[3] = -1e-3
+    f[4] += 1e-3
+    a, it = ora.alpha(f, fe, u, 1.0)
+    assert it == -1
+
+
 def test_alpha_equilibrium_is_bgk(ora):
     # f = f_eq: Delta = 0, the collision vanishes and alpha takes the BGK value 2.
     u = np.array([0.03, -0.02, 0.01])
@@ -135,7 +177,7 @@ def test_alpha_no_root_falls_back(ora):
     d[1], d[2] = 1e-9, -1e-9
     f = fe - d
     x = d / f
-    L = np.sum(d * (np.log(fe / (w * rho)) - np.log1p(x)))
+    L = np.sum(d * np.log(f / (w * rho)))
     assert L >= 0
     a, it = ora.alpha(f, fe, u, rho)
     amax = np.min(-1 / x[x < 0])
