@@ -145,6 +145,12 @@ elbm_status elbm_set_box(elbm_ctx *ctx, int32_t box, const uint8_t *node_type, c
  * elbm_read_* calls return. */
 elbm_status elbm_step(elbm_ctx *ctx, int32_t nsteps, int32_t record);
 
+/* enable != 0 (the default): elbm_step replays pairs of unrecorded steps as a
+ * captured two-step hipGraph on the bound stream (built on first use, kept
+ * with the context; never on the null stream or while timing).  enable == 0:
+ * every kernel is launched directly.  Results are bitwise identical. */
+elbm_status elbm_set_graphs(elbm_ctx *ctx, int32_t enable);
+
 /* Waits for the stream; returns ELBM_ENONFINITE if any step produced a
  * non-finite population since bind (sticky). */
 elbm_status elbm_sync(elbm_ctx *ctx);

@@ -56,7 +56,18 @@ struct elbm_ctx {
   size_t ev_used = 0;
   double phase_ms[ELBM_NPHASES] = {0, 0, 0, 0, 0};
   int64_t timed_steps = 0;
+  // captured two-step graphs, indexed by the starting population parity
+  bool use_graphs = true;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  void drop_graphs() {
+    for (hipGraphExec_t &g : graph_exec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
   ~elbm_ctx() {
+    drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -157,55 +168,94 @@ elbm_status collect_timing(elbm_ctx *c) {
   return ELBM_OK;
 }
 
+// Enqueues one time step (every kernel of Sec. II.C) on the bound stream and
+// flips the population parity.
 template <typename T, typename F, int C>
-elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
+elbm_status enqueue_step(elbm_ctx *c, int rec) {
   const Model M = make_model(c->P);
   const dim3 grid(c->nblocks), blk(BLK);
   const int nb = (int)c->boxes.size();
-  for (int it = 0; it < nsteps; ++it) {
-    Ptrs<T, F> a = make_ptrs<T, F>(c);
-    const int rec = record && (it == nsteps - 1);
-    hipEvent_t *ev = nullptr;
-    if (c->timing) {
-      const size_t per = ELBM_NPHASES + 1;
-      if (c->ev_used + per > 6000) {  // bound the pool: fold what is recorded so far
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        elbm_status st = collect_timing(c);
-        if (st) return st;
-      }
-      while (c->ev_pool.size() < c->ev_used + per) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->ev_pool.push_back(e);
-      }
-      ev = c->ev_pool.data() + c->ev_used;
-      c->ev_used += per;
+  Ptrs<T, F> a = make_ptrs<T, F>(c);
+  hipEvent_t *ev = nullptr;
+  if (c->timing) {
+    const size_t per = ELBM_NPHASES + 1;
+    if (c->ev_used + per > 6000) {  // bound the pool: fold what is recorded so far
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      elbm_status st = collect_timing(c);
+      if (st) return st;
     }
-    mark(c, ev, 0);
-    hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
-    mark(c, ev, 1);
-    hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
-    hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
-    hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M);
-    hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
-    mark(c, ev, 2);
-    for (int sw = 0; sw < c->P.sor_sweeps; ++sw) {
-      hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0);
-      hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1);
+    while (c->ev_pool.size() < c->ev_used + per) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
     }
-    if (c->any_gauge) {
-      hipLaunchKernelGGL((k_phi_partials<T, F>), grid, blk, 0, c->stream, a);
-      hipLaunchKernelGGL(k_phi_mean, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal);
-      hipLaunchKernelGGL((k_phi_sub<T, F>), grid, blk, 0, c->stream, a);
-    }
-    mark(c, ev, 3);
-    hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
-    mark(c, ev, 4);
-    hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
-    mark(c, ev, 5);
-    c->parity ^= 1;
+    ev = c->ev_pool.data() + c->ev_used;
+    c->ev_used += per;
   }
+  mark(c, ev, 0);
+  hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 1);
+  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
+  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M);
+  hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 2);
+  for (int sw = 0; sw < c->P.sor_sweeps; ++sw) {
+    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0);
+    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1);
+  }
+  if (c->any_gauge) {
+    hipLaunchKernelGGL((k_phi_partials<T, F>), grid, blk, 0, c->stream, a);
+    hipLaunchKernelGGL(k_phi_mean, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal);
+    hipLaunchKernelGGL((k_phi_sub<T, F>), grid, blk, 0, c->stream, a);
+  }
+  mark(c, ev, 3);
+  hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 4);
+  hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
+  mark(c, ev, 5);
+  c->parity ^= 1;
   HIPCHK(c, hipGetLastError());
+  return ELBM_OK;
+}
+
+// nsteps steps.  Without per-phase timing, on a non-null stream, pairs of
+// unrecorded steps replay a captured two-step hipGraph (one per starting
+// parity, built on first use and kept with the context): the 2 x (7 + 2k)
+// launches of a pair become one graph launch.
+template <typename T, typename F, int C>
+elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
+  int direct = nsteps;
+  if (!c->timing && c->use_graphs && c->stream != nullptr) {
+    const int pairs = (record ? nsteps - 1 : nsteps) / 2;
+    if (pairs > 0) {
+      hipGraphExec_t &ge = c->graph_exec[c->parity];
+      if (!ge) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        elbm_status s1 = enqueue_step<T, F, C>(c, 0);
+        elbm_status s2 = s1 ? s1 : enqueue_step<T, F, C>(c, 0);
+        hipError_t ec = hipStreamEndCapture(c->stream, &g);
+        if (s2) {
+          if (g) (void)hipGraphDestroy(g);
+          return s2;
+        }
+        if (ec != hipSuccess) return fail(c, ELBM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+          ge = nullptr;
+          return fail(c, ELBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+      }
+      for (int i = 0; i < pairs; ++i) HIPCHK(c, hipGraphLaunch(ge, c->stream));
+      direct = nsteps - 2 * pairs;
+    }
+  }
+  for (int it = 0; it < direct; ++it) {
+    elbm_status st = enqueue_step<T, F, C>(c, record && it == direct - 1);
+    if (st) return st;
+  }
   return ELBM_OK;
 }
 
@@ -376,7 +426,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_fb = take((size_t)C * NQ * N * ep);
   c->o_rho = take((size_t)C * N * e);
   c->o_psi = take((size_t)C * N * e);
-  c->o_grad = take(3 * (size_t)N * e);
+  c->o_grad = take(4 * (size_t)N * e);
   c->o_bulk = take((size_t)N * e);
   c->o_surf = take((size_t)N * e);
   c->o_q = take((size_t)N * e);
@@ -409,6 +459,7 @@ elbm_status elbm_bind(elbm_ctx *c, void *arena, size_t bytes, void *stream) {
   if (!c) return ELBM_EINVAL;
   if (!arena || ((uintptr_t)arena & 255)) return fail(c, ELBM_EINVAL, "arena must be non-null and 256-byte aligned");
   if (bytes < c->total) return fail(c, ELBM_ENOMEM, "arena smaller than elbm_required_bytes");
+  c->drop_graphs();
   c->base = (char *)arena;
   c->stream = (hipStream_t)stream;
   c->parity = 0;
@@ -440,6 +491,7 @@ elbm_status elbm_set_box(elbm_ctx *c, int32_t box, const uint8_t *type, const do
   }
   B.has_dirichlet = dir ? 1 : 0;
   B.n_unknown = (int32_t)nu;
+  c->drop_graphs();  // the gauge launches depend on the Dirichlet flags
   c->any_gauge = false;
   for (auto &d : c->bdev) if (!d.has_dirichlet) c->any_gauge = true;
   HIPCHK(c, hipMemcpy(c->base + c->o_boxes + sizeof(BoxDev) * box, &B, sizeof(BoxDev), hipMemcpyHostToDevice));
@@ -455,6 +507,14 @@ elbm_status elbm_step(elbm_ctx *c, int32_t nsteps, int32_t record) {
     ELBM_DISPATCH(c, return launch_steps<T, F, 2>(c, nsteps, record))
   }
   ELBM_DISPATCH(c, return launch_steps<T, F, 1>(c, nsteps, record))
+}
+
+elbm_status elbm_set_graphs(elbm_ctx *c, int32_t enable) {
+  if (!c) return ELBM_EINVAL;
+  if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->use_graphs = enable != 0;
+  if (!c->use_graphs) c->drop_graphs();
+  return ELBM_OK;
 }
 
 elbm_status elbm_sync(elbm_ctx *c) {

@@ -5,7 +5,7 @@
 //
 // Per step (Sec. II.C):
 //   k_density      pull + component densities rho_s and psi_s = 1 - exp(-rho_s)
-//   k_gradient     19-point gradient of the liquid density
+//   k_gradient     19-point gradient of the liquid density -> unit normal, |grad|^2
 //   k_interface    curvature K = -div n, theta, charge weights, block partials
 //   k_charge_coef  per-box deterministic reduce -> charge scale and jellium
 //   k_charge_rhs   q and the Poisson right-hand side
@@ -58,8 +58,9 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
   }
 }
 
-// 19-point isotropic gradient (1/c_s^2) sum_p w_p c_p rho_A(r + c_p); a solid
-// or outside neighbour takes the centre value.
+// 19-point isotropic gradient G = (1/c_s^2) sum_p w_p c_p rho_A(r + c_p) (a
+// solid or outside neighbour takes the centre value), stored as the unit
+// normal n = G/|G| (0 where |G| <= 1e-12) and |G|^2.
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
   Node nd;
@@ -81,28 +82,20 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
     g1 /= F(CS2);
     g2 /= F(CS2);
   }
-  a.grad[nd.g] = g0;
-  a.grad[a.N + nd.g] = g1;
-  a.grad[2 * a.N + nd.g] = g2;
+  const F gg = g0 * g0 + g1 * g1 + g2 * g2;
+  const F m = sqrt(gg);
+  const bool ok = m > F(1e-12);
+  a.grad[nd.g] = ok ? g0 / m : F(0);
+  a.grad[a.N + nd.g] = ok ? g1 / m : F(0);
+  a.grad[2 * a.N + nd.g] = ok ? g2 / m : F(0);
+  a.grad[3 * a.N + nd.g] = gg;
 }
 
-template <typename T, typename F>
-__device__ __forceinline__ void unit_normal(const Ptrs<T, F> &a, int64_t i, F &n0, F &n1, F &n2) {
-  const F g0 = a.grad[i], g1 = a.grad[a.N + i], g2 = a.grad[2 * a.N + i];
-  const F m = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
-  if (m > F(1e-12)) {
-    n0 = g0 / m;
-    n1 = g1 / m;
-    n2 = g2 / m;
-  } else {
-    n0 = n1 = n2 = F(0);
-  }
-}
-
-// Mean curvature K = -div n (n = grad rho_A / |grad rho_A|, Eq.
-// surface-curvature with the sign that makes a convex drop positive),
-// smoothed Heaviside theta, the two charge weights of Eqs. surface-q2 /
-// surface-q3 and their per-block sums (all nodes, Poisson-unknown nodes).
+// Mean curvature K = -div n (Eq. surface-curvature, with the sign that makes a
+// convex drop positive; a solid or outside neighbour takes the centre
+// normal), smoothed Heaviside theta, the two charge weights of Eqs.
+// surface-q2 / surface-q3 and their per-block sums (all nodes, Poisson-unknown
+// nodes).
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
   Node nd;
@@ -112,25 +105,27 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
     const uint8_t tt = a.type[nd.g];
     F bulk = F(0), surf = F(0);
     if ((tt & 3) != K_SOLID) {
-      F c0, c1, c2;
-      unit_normal(a, nd.g, c0, c1, c2);
+      const F c0 = a.grad[nd.g], c1 = a.grad[a.N + nd.g], c2 = a.grad[2 * a.N + nd.g];
       F div = F(0);
 #pragma unroll
       for (int p = 1; p < NQ; ++p) {
         const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
         F n0 = c0, n1 = c1, n2 = c2;
-        if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) unit_normal(a, nd.B.off + m, n0, n1, n2);
+        if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) {
+          const int64_t gm = nd.B.off + m;
+          n0 = a.grad[gm];
+          n1 = a.grad[a.N + gm];
+          n2 = a.grad[2 * a.N + gm];
+        }
         div += F(wgt(p)) * (F(kCx[p]) * n0 + F(kCy[p]) * n1 + F(kCz[p]) * n2);
       }
       const F K = -div / F(CS2);
       const F rA = a.rho[nd.g];
       const F theta = F(0.5) * (F(1) + tanh((rA - F(M.rho_th)) / F(M.w_theta)));
       bulk = rA * theta;
-      const F g0 = a.grad[nd.g], g1 = a.grad[a.N + nd.g], g2 = a.grad[2 * a.N + nd.g];
-      const F gg = g0 * g0 + g1 * g1 + g2 * g2;
       F wK = F(1);
       if (M.curvature) wK += sqrt(sqrt(fmax(K, F(0)) / F(M.K_d)));
-      surf = gg * wK;
+      surf = a.grad[3 * a.N + nd.g] * wK;
     }
     a.bulk[nd.g] = bulk;
     a.surf[nd.g] = surf;

@@ -65,7 +65,7 @@ SYMBOLS = [
     "elbm_abi_version", "elbm_create", "elbm_required_bytes", "elbm_bind", "elbm_set_box", "elbm_step",
     "elbm_sync", "elbm_read_moments", "elbm_read_potential", "elbm_read_charge", "elbm_read_alpha",
     "elbm_get_populations", "elbm_set_populations", "elbm_set_potential", "elbm_diagnostics",
-    "elbm_set_timing", "elbm_timing", "elbm_last_error", "elbm_destroy",
+    "elbm_set_graphs", "elbm_set_timing", "elbm_timing", "elbm_last_error", "elbm_destroy",
 ]
 PHASES = ["density", "charge", "poisson", "efield", "collide"]
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.elbm_set_populations.argtypes = [vp, i32, vp]
     L.elbm_set_potential.argtypes = [vp, i32, vp]
     L.elbm_diagnostics.argtypes = [vp, i32, ct.POINTER(elbm_diag)]
+    L.elbm_set_graphs.argtypes = [vp, i32]
     L.elbm_set_timing.argtypes = [vp, i32]
     L.elbm_timing.argtypes = [vp, vp, vp]
     L.elbm_last_error.restype = ct.c_char_p
@@ -179,7 +180,10 @@ class Lattice:
         self.arena = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = self.arena.data_ptr()
         aligned = (ptr + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the step graphs cannot be
+        # captured on the null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.arena.record_stream(self.stream)
         self._check(self.L.elbm_bind(self.h, ct.c_void_p(aligned), self.nbytes, ct.c_void_p(self.stream.cuda_stream)))
         for i, b in enumerate(self.boxes):
             self.set_box(i, b)
@@ -267,6 +271,9 @@ class Lattice:
         return dict(mass=list(d.mass), momentum=list(d.momentum), alpha_min=d.alpha_min,
                     alpha_max=d.alpha_max, alpha_mean=d.alpha_mean, mean_newton_iters=d.mean_newton_iters,
                     n_fallback=d.n_fallback, n_negative=d.n_negative, n_collisions=d.n_collisions)
+
+    def set_graphs(self, enable: bool = True):
+        self._check(self.L.elbm_set_graphs(self.h, int(bool(enable))))
 
     def set_timing(self, enable: bool = True):
         self._check(self.L.elbm_set_timing(self.h, int(bool(enable))))
