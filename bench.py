@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--alpha-guess", default="series", choices=["series", "standard"],
+    ap.add_argument("--alpha-guess", default="series", choices=["series", "standard", "mlp"],
                     help="initial guess of the alpha Newton iteration for the reported value")
     ap.add_argument("--single-mode", action="store_true",
                     help="time only the reported guess (no comparison run)")
@@ -88,12 +88,19 @@ def main():
     box = wl.boxes[0]
     nodes = wl.nodes
     esz = 8 if wl.dtype == "f64" else 4
-    modes = [args.alpha_guess] + [m for m in ("standard", "series") if m != args.alpha_guess]
+    from paper_1612_05404_amd import learned
+    have_net = os.path.exists(learned.WEIGHTS)
+    if args.alpha_guess == "mlp" and not have_net:
+        sys.exit(f"--alpha-guess mlp needs the stored network {learned.WEIGHTS}")
+    modes = [args.alpha_guess] + [m for m in ("standard", "series", "mlp")
+                                  if m != args.alpha_guess and (m != "mlp" or have_net)]
     results = {}
     for mode in modes:
         print(f"[bench] workload {wl.name} {box.nx}x{box.ny}x{box.nz} dtype {wl.dtype} sor_sweeps "
               f"{wl.params.sor_sweeps} alpha guess {mode}", file=sys.stderr, flush=True)
         lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
+        if mode == "mlp":
+            lat.mlp_set_weights(learned.load_weights())
         lat.step(args.warmup, record=False)
         lat.sync()
         # timed region: K steps as replayed step graphs, wall clock between

@@ -64,8 +64,9 @@ enum { ELBM_CHARGE_CONSERVING = 0, ELBM_CHARGE_GENERATOR = 1 };
 /* Initial guess of the alpha Newton iteration; every guess is polished to the
  * same stopping rule.  STANDARD: alpha0 = 2 (the BGK value).  SERIES: root of
  * the degree-7 truncation of the entropy balance in powers of alpha (no
- * logarithms), used where that truncation is accurate.  MLP: the learned
- * starter. */
+ * logarithms), used inside the positivity interval while alpha0 max|x| < 1.2.
+ * MLP: the series starter where it is used, the learned starter elsewhere
+ * (see elbm_mlp_* below). */
 enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1, ELBM_GUESS_SERIES = 2 };
 
 /* Model constants shared by every box of a context. */
@@ -195,6 +196,46 @@ elbm_status elbm_set_timing(elbm_ctx *ctx, int32_t enable);
  * phase ms[ELBM_NPHASES] and the number of timed steps since timing was
  * enabled (either pointer may be NULL), then restarts the accumulation. */
 elbm_status elbm_timing(elbm_ctx *ctx, double *ms, int64_t *steps);
+
+/* ---- Learned starter of the alpha Newton iteration (ELBM_GUESS_MLP) ----
+ * A 20 -> 32 -> 32 -> 1 SiLU network, BF16 weights and activations with FP32
+ * accumulation on the matrix cores.  Input per node and component: the 19
+ * ratios r_p = f_p/f_eq_p as z_p = (r_p - 1)/s and s = max_p |r_p - 1| (no
+ * starter when a population or equilibrium entry is not positive or s is 0
+ * or above 1); output y; starter alpha0 = 2 + s y.  In the update it serves
+ * the nodes where the series starter is rejected (large non-equilibrium, at
+ * interfaces); Newton then polishes to the same rule as every other starter.
+ * Parameters: FP32 vector of 1761 floats, in order W1[32][20], b1[32],
+ * W2[32][32], b2[32], w3[32], b3. */
+
+/* Sets the parameters (host, n = 1761) and clears the optimiser state. */
+elbm_status elbm_mlp_set_weights(elbm_ctx *ctx, const float *w, int64_t n);
+/* Copies the current parameters to the host (n = 1761). */
+elbm_status elbm_mlp_get_weights(elbm_ctx *ctx, float *w, int64_t n);
+/* Inference on the bound stream: device X float [M][20] -> device Y float [M]. */
+elbm_status elbm_mlp_forward(elbm_ctx *ctx, const void *dX, void *dY, int64_t M);
+/* Gradient of L = (1/2M) sum_i (y_i - T_i)^2 over device X [M][20], T [M]
+ * (synchronous): grad [1761] in parameter order and the loss, host pointers
+ * (either may be NULL). */
+elbm_status elbm_mlp_grad(elbm_ctx *ctx, const void *dX, const void *dT, int64_t M, float *grad,
+                          float *loss);
+/* steps (<= 4096) Adam steps (beta 0.9, 0.999, eps 1e-8, learning rate lr) on
+ * consecutive batches of `batch` samples of device X [M][20], T [M], wrapping at
+ * M (the caller shuffles); losses [steps] (host, may be NULL) receives each
+ * batch loss.  Synchronous. */
+elbm_status elbm_mlp_train(elbm_ctx *ctx, const void *dX, const void *dT, int64_t M, int32_t batch,
+                           int32_t steps, float lr, float *losses);
+/* Training samples from the current state of one box (the populations the
+ * next step pulls): for node n and component s at index s * N + n, the
+ * starter input feat [.][20] (z, s), the target (alpha* - 2)/s with alpha*
+ * the plain Newton root from 2, the scale s, and a flag: 0 at non-fluid
+ * nodes, without features, or where the plain solve fell back; 1 a usable
+ * sample; 2 a usable sample at a node the learned starter serves (the series
+ * starter is rejected there).
+ * Device pointers: float [C*N][20], float [C*N], float [C*N], int32 [C*N].
+ * Synchronous. */
+elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dTarget, void *dScale,
+                               void *dValid);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *elbm_last_error(const elbm_ctx *ctx);

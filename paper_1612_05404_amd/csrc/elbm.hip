@@ -44,6 +44,9 @@ struct elbm_ctx {
   // arena offsets (bytes)
   size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_reca,
       o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_scal, o_cnt, o_err, total;
+  // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
+  size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
+  int64_t adam_t = 0;
   char *base = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -144,6 +147,17 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   return a;
 }
 
+constexpr int MLP_MAX_STEPS = 4096;  // optimiser steps per elbm_mlp_train call
+
+MlpDev make_mlp(elbm_ctx *c) {
+  MlpDev W;
+  W.w1 = (const __bf16 *)(c->base + c->o_mw1);
+  W.w2 = (const __bf16 *)(c->base + c->o_mw2);
+  W.w2t = (const __bf16 *)(c->base + c->o_mw2t);
+  W.p = (const float *)(c->base + c->o_mp);
+  return W;
+}
+
 double *stage(elbm_ctx *c, int plane) { return (double *)(c->base + c->o_stage) + (int64_t)plane * c->maxN; }
 
 // Records the next timing event of the current step (no-op when timing is off).
@@ -212,7 +226,10 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   mark(c, ev, 3);
   hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 4);
-  hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
+  if (M.alpha_guess == ELBM_GUESS_MLP)
+    hipLaunchKernelGGL((k_collide<T, F, C, true>), grid, blk, 0, c->stream, a, M, make_mlp(c), rec);
+  else
+    hipLaunchKernelGGL((k_collide<T, F, C, false>), grid, blk, 0, c->stream, a, M, make_mlp(c), rec);
   mark(c, ev, 5);
   c->parity ^= 1;
   HIPCHK(c, hipGetLastError());
@@ -382,7 +399,9 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   if (P->charge_model != ELBM_CHARGE_CONSERVING && P->charge_model != ELBM_CHARGE_GENERATOR) return ELBM_EINVAL;
   if (!(P->w_theta > 0.0) || !(P->K_d > 0.0) || !(P->nu0 > 0.0) || !(P->newton_rtol > 0.0)) return ELBM_EINVAL;
   if (P->carreau && !(P->nu_inf > 0.0 && P->lam >= 0.0)) return ELBM_EINVAL;
-  if (P->alpha_guess != ELBM_GUESS_STANDARD && P->alpha_guess != ELBM_GUESS_SERIES) return ELBM_EINVAL;
+  if (P->alpha_guess != ELBM_GUESS_STANDARD && P->alpha_guess != ELBM_GUESS_SERIES &&
+      P->alpha_guess != ELBM_GUESS_MLP)
+    return ELBM_EINVAL;
   elbm_ctx *c = new (std::nothrow) elbm_ctx();
   if (!c) return ELBM_ENOMEM;
   c->P = *P;
@@ -444,6 +463,15 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_scal = take(sizeof(double) * NSCAL * nboxes);
   c->o_cnt = take(sizeof(unsigned long long) * NCNT * nboxes);
   c->o_err = take(sizeof(uint32_t) * 4);
+  c->o_mp = take(sizeof(float) * MLP_NPARAM);
+  c->o_mm = take(sizeof(float) * MLP_NPARAM);
+  c->o_mv = take(sizeof(float) * MLP_NPARAM);
+  c->o_mw1 = take(2 * 32 * 32);
+  c->o_mw2 = take(2 * 32 * 32);
+  c->o_mw2t = take(2 * 32 * 32);
+  c->o_mgrad = take(sizeof(float) * (MLP_NPARAM + 1));
+  c->o_mpart = take(sizeof(float) * MLP_GGRID * MLP_GRAD_SLOTS);
+  c->o_mloss = take(sizeof(float) * MLP_MAX_STEPS);
   c->total = o;
   *out = c;
   return ELBM_OK;
@@ -670,6 +698,114 @@ elbm_status elbm_timing(elbm_ctx *c, double *ms, int64_t *steps) {
   if (steps) *steps = c->timed_steps;
   for (double &v : c->phase_ms) v = 0.0;
   c->timed_steps = 0;
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_set_weights(elbm_ctx *c, const float *w, int64_t n) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!w || n != MLP_NPARAM) return fail(c, ELBM_EINVAL, "weights: need 1761 floats");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->base + c->o_mp, w, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(c->base + c->o_mm, 0, sizeof(float) * MLP_NPARAM));
+  HIPCHK(c, hipMemset(c->base + c->o_mv, 0, sizeof(float) * MLP_NPARAM));
+  c->adam_t = 0;
+  hipLaunchKernelGGL(k_mlp_refresh, dim3(1), dim3(BLK), 0, c->stream, (const float *)(c->base + c->o_mp),
+                     (__bf16 *)(c->base + c->o_mw1), (__bf16 *)(c->base + c->o_mw2),
+                     (__bf16 *)(c->base + c->o_mw2t));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_get_weights(elbm_ctx *c, float *w, int64_t n) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!w || n != MLP_NPARAM) return fail(c, ELBM_EINVAL, "weights: need 1761 floats");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(w, c->base + c->o_mp, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_forward(elbm_ctx *c, const void *dX, void *dY, int64_t M) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!dX || !dY || M < 0) return fail(c, ELBM_EINVAL, "mlp_forward: bad arguments");
+  if (M == 0) return ELBM_OK;
+  const int64_t nb = (M + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(BLK), 0, c->stream, make_mlp(c),
+                     (const float *)dX, (float *)dY, M);
+  HIPCHK(c, hipGetLastError());
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_grad(elbm_ctx *c, const void *dX, const void *dT, int64_t M, float *grad, float *loss) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!dX || !dT || M <= 0) return fail(c, ELBM_EINVAL, "mlp_grad: bad arguments");
+  float *part = (float *)(c->base + c->o_mpart), *g = (float *)(c->base + c->o_mgrad);
+  hipLaunchKernelGGL(k_mlp_grad, dim3(MLP_GGRID), dim3(MLP_GBLK), 0, c->stream, make_mlp(c), (const float *)dX,
+                     (const float *)dT, (int64_t)0, M, 1.0f / (float)M, part);
+  hipLaunchKernelGGL(k_mlp_sum, dim3(1), dim3(BLK), 0, c->stream, (const float *)part, MLP_GGRID, g, (float *)nullptr);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (grad) HIPCHK(c, hipMemcpy(grad, g, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  if (loss) HIPCHK(c, hipMemcpy(loss, g + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost));
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_train(elbm_ctx *c, const void *dX, const void *dT, int64_t M, int32_t batch, int32_t steps,
+                           float lr, float *losses) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!dX || !dT || M <= 0 || batch <= 0 || steps < 0 || steps > MLP_MAX_STEPS || !(lr > 0.0f))
+    return fail(c, ELBM_EINVAL, "mlp_train: bad arguments");
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float *part = (float *)(c->base + c->o_mpart), *g = (float *)(c->base + c->o_mgrad);
+  float *lbuf = (float *)(c->base + c->o_mloss);
+  int64_t start = 0;
+  for (int i = 0; i < steps; ++i) {
+    if (start >= M) start = 0;
+    const int64_t B = (start + batch <= M) ? batch : M - start;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(MLP_GGRID), dim3(MLP_GBLK), 0, c->stream, make_mlp(c), (const float *)dX,
+                       (const float *)dT, start, B, 1.0f / (float)B, part);
+    hipLaunchKernelGGL(k_mlp_sum, dim3(1), dim3(BLK), 0, c->stream, (const float *)part, MLP_GGRID, g, lbuf + i);
+    c->adam_t += 1;
+    const float bc1 = 1.0f - powf(b1, (float)c->adam_t), bc2 = 1.0f - powf(b2, (float)c->adam_t);
+    hipLaunchKernelGGL(k_mlp_adam, dim3(1), dim3(BLK), 0, c->stream, (float *)(c->base + c->o_mp),
+                       (float *)(c->base + c->o_mm), (float *)(c->base + c->o_mv), (const float *)g, lr, b1, b2, eps,
+                       bc1, bc2);
+    hipLaunchKernelGGL(k_mlp_refresh, dim3(1), dim3(BLK), 0, c->stream, (const float *)(c->base + c->o_mp),
+                       (__bf16 *)(c->base + c->o_mw1), (__bf16 *)(c->base + c->o_mw2),
+                       (__bf16 *)(c->base + c->o_mw2t));
+    start += B;
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (losses && steps > 0) HIPCHK(c, hipMemcpy(losses, lbuf, sizeof(float) * steps, hipMemcpyDeviceToHost));
+  return ELBM_OK;
+}
+
+elbm_status elbm_alpha_samples(elbm_ctx *c, int32_t box, void *dFeat, void *dTarget, void *dScale,
+                               void *dValid) {
+  elbm_status st = check_box_arg(c, box);
+  if (st) return st;
+  if (!dFeat || !dTarget || !dScale || !dValid) return fail(c, ELBM_EINVAL, "alpha_samples: NULL output");
+  const Model M = make_model(c->P);
+  const dim3 grid(c->nblocks), blk(BLK);
+  if (c->P.ncomp == 2) {
+    ELBM_DISPATCH(c, {
+      hipLaunchKernelGGL((k_alpha_samples<T, F, 2>), grid, blk, 0, c->stream, make_ptrs<T, F>(c), M, box,
+                         (float *)dFeat, (float *)dTarget, (float *)dScale, (int32_t *)dValid);
+    } break)
+  } else {
+    ELBM_DISPATCH(c, {
+      hipLaunchKernelGGL((k_alpha_samples<T, F, 1>), grid, blk, 0, c->stream, make_ptrs<T, F>(c), M, box,
+                         (float *)dFeat, (float *)dTarget, (float *)dScale, (int32_t *)dValid);
+    } break)
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return ELBM_OK;
 }
 

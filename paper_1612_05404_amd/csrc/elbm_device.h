@@ -217,19 +217,35 @@ __device__ __forceinline__ double phi_of(double y, double l) {
 // as sum_p Delta_p log1p((f_p - w_p rho)/(w_p rho)) (one log per direction,
 // no cancellation).  g is convex on the positivity interval (0, a_max) with
 // g(0) = 0, g'(0) = L, so a root exists iff L < 0.
-// Newton from a0 = 2, or from the series starter when `series` is set: the
-// root of the degree-7 truncation of g(a)/a = L + sum_k (-1)^k a^(k-1) M_k /
-// (k(k-1)), M_k = sum_p f_p x_p^k, accepted when a0 max|x| < 0.2 (truncation
-// below 1e-8 relative).  Either way the result is polished to the same
-// stopping rule.  Returns the update count in `iters`, or -1 with the
-// fallback min(2, 0.99 a_max) when there is no root, Newton does not
-// converge, or a population is not positive (H undefined).
-// f: the node's 19 populations of one component, xs: scratch for x; both are
-// thread-private LDS columns (element p at offset p * BLK), which keeps the
-// p loops rolled and the register footprint small.  rho, u: FP64 moments of f.
+// Starters: 2 (ELBM_GUESS_STANDARD); the series starter (ELBM_GUESS_SERIES),
+// the root of the degree-7 truncation of
+// g(a)/a = L + sum_k (-1)^k a^(k-1) M_k / (k(k-1)), M_k = sum_p f_p x_p^k,
+// accepted inside the positivity interval while a0 max|x| < SERIES_ACCEPT
+// (beyond 0.2 the truncation is no longer small, but up to about 1 the root
+// is still a closer start than 2: fewer updates at interface nodes); the
+// learned starter (ELBM_GUESS_MLP) takes the series starter where it is
+// accepted and the network's a0 where it is not (and a0 lies in the
+// positivity interval).  Every starter is polished by Newton to the same
+// stopping rule.  The update count goes to `iters`, or -1 with the fallback
+// min(2, 0.99 a_max) when there is no root, Newton does not converge, or a
+// population is not positive (H undefined).
+// f: the node's 19 populations of one component (thread-private LDS column,
+// element p at offset p * BLK); xs: scratch for x (element p at p * XSTRIDE
+// in the wave's own LDS block).  Both keep the p loops rolled and the register
+// footprint small.  rho, u: FP64 moments of f.
+constexpr int XSTRIDE = 64;  // stride of a thread's x column in its wave's LDS block
+constexpr double SERIES_ACCEPT = 1.2;
+
+// State between the set-up pass and the Newton polish.
+struct AlphaSetup {
+  double L, amax, xmax, a;  // a: the starter so far
+  int state;                // 0: Newton needed, 1: done (a, iters 0), 2: fallback
+  bool want_learned;        // the learned starter would be used here
+};
+
 template <typename T>
-__device__ double alpha_solve(const T *f, double *xs, double rho, double ux, double uy, double uz,
-                              bool series, double rtol, int maxit, int &iters) {
+__device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double rho, double ux, double uy,
+                                                  double uz, int guess) {
   const double uu = ux * ux + uy * uy + uz * uz;
   const double irho = rcp_nr(rho);
   double xmax = 0.0, amax = INFINITY, L = 0.0;
@@ -242,7 +258,7 @@ __device__ double alpha_solve(const T *f, double *xs, double rho, double ux, dou
     const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
     const double x = d * rcp_nr(fp);
     nonpos |= !(fp > 0.0);
-    xs[p * BLK] = x;
+    xs[p * XSTRIDE] = x;
     xmax = fmax(xmax, fabs(x));
     if (x < 0.0) amax = fmin(amax, -rcp_nr(x));
     L += d * log1p_fast((fp - wr) * (irho * (1.0 / wgt(p))));
@@ -258,16 +274,22 @@ __device__ double alpha_solve(const T *f, double *xs, double rho, double ux, dou
     M6 += t;
     M7 += t * x;
   }
+  AlphaSetup st;
+  st.L = L;
+  st.amax = amax;
+  st.xmax = xmax;
+  st.a = 2.0;
+  st.want_learned = false;
   if (nonpos) {  // H(f) is undefined for a non-positive population
-    iters = -1;
-    return fmin(2.0, 0.99 * amax);
+    st.state = 2;
+    return st;
   }
   if (xmax < 1e-12) {
-    iters = 0;
-    return 2.0;
+    st.state = 1;
+    return st;
   }
-  double a = 2.0;
-  if (series && L < 0.0) {
+  st.state = L < 0.0 ? 0 : 2;
+  if (st.state == 0 && (guess == ELBM_GUESS_SERIES || guess == ELBM_GUESS_MLP)) {
     // Newton on the truncated series from 2 (no logarithms)
     double b = 2.0;
 #pragma unroll 1
@@ -277,16 +299,30 @@ __device__ double alpha_solve(const T *f, double *xs, double rho, double ux, dou
       if (!(dq > 0.0)) break;
       b -= q / dq;
     }
-    if (b > 0.0 && b < amax && b * xmax < 0.2) a = b;
+    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) st.a = b;
+    else st.want_learned = guess == ELBM_GUESS_MLP;
   }
-  if (!(a > 0.0 && a < amax)) a = 0.5 * fmin(amax, 4.0);
-  if (L < 0.0) {
+  return st;
+}
+
+template <typename T>
+__device__ __forceinline__ double alpha_newton(const T *f, const double *xs, AlphaSetup st, double a0, double rtol,
+                                               int maxit, int &iters) {
+  if (st.state == 1) {
+    iters = 0;
+    return 2.0;
+  }
+  if (st.state == 0) {
+    double a = st.a;
+    if (st.want_learned && a0 > 0.0 && a0 < st.amax) a = a0;
+    if (!(a > 0.0 && a < st.amax)) a = 0.5 * fmin(st.amax, 4.0);
+    const double L = st.L, amax = st.amax;
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L;
 #pragma unroll 4
       for (int p = 0; p < NQ; ++p) {
         const double fp = double(f[p * BLK]);
-        const double x = xs[p * BLK];
+        const double x = xs[p * XSTRIDE];
         const double y = a * x;
         const double l = log1p_fast(y);
         S += fp * phi_of(y, l);
@@ -309,7 +345,30 @@ __device__ double alpha_solve(const T *f, double *xs, double rho, double ux, dou
     }
   }
   iters = -1;
-  return fmin(2.0, 0.99 * amax);
+  return fmin(2.0, 0.99 * st.amax);
+}
+
+// Input of the learned starter from the x_p of the set-up pass: with
+// r_p = f_p / f_eq_p = 1/(1 + x_p), z_p = (r_p - 1)/s (z[0..18]) and
+// s = max_p |r_p - 1|.  Valid when every f_eq_p is positive (x_p > -1) and
+// 0 < s <= 1.
+__device__ __forceinline__ bool features_from_x(const double *xs, float *z, double &scale) {
+  double r[NQ];
+  bool ok = true;
+  double sc = 0.0;
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) {
+    const double x = xs[p * XSTRIDE];
+    ok &= x > -1.0;
+    r[p] = -x * rcp_nr(1.0 + x);
+    sc = fmax(sc, fabs(r[p]));
+  }
+  ok &= (sc > 0.0) && (sc <= 1.0);
+  const double is = ok ? rcp_nr(sc) : 0.0;
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) z[p] = ok ? float(r[p] * is) : 0.0f;
+  scale = sc;
+  return ok;
 }
 
 // Matrix 2-norm of a symmetric 3x3 (largest |eigenvalue|), cyclic Jacobi

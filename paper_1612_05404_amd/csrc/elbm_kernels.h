@@ -17,6 +17,7 @@
 #pragma once
 
 #include "elbm_device.h"
+#include "elbm_mlp.h"
 
 namespace elbm {
 
@@ -266,22 +267,49 @@ __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
   a.e2[nd.g] = e0 * e0 + e1 * e1 + e2 * e2;
 }
 
+// LDS copy of the network, present only in the learned-starter variant.
+template <bool LEARN> struct LearnLds {};
+template <> struct LearnLds<true> { MlpShared net; };
+
+// x_p = (f_eq_p - f_p)/f_p of every direction into the wave's LDS scratch,
+// with the same expression as the alpha set-up pass (bit-identical).
+template <typename T>
+__device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, double ux, double uy, double uz) {
+  const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll 4
+  for (int p = 0; p < NQ; ++p) {
+    const double fp = double(f[p * BLK]);
+    xs[p * XSTRIDE] = (feq<double>(p, rho, ux, uy, uz, uu) - fp) * rcp_nr(fp);
+  }
+}
+
 // The collision (Eq. lattice-b) at fluid nodes with every force term.
 // Forces come first (fields only); then each component in turn: pull its 19
-// populations, FP64 moments, FP64 alpha, viscosity, collision, store.
-template <typename T, typename F, int C>
-__global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int record) {
-  // thread-private LDS columns: populations of the current component and x_p
+// populations and FP64 moments, (LEARN) run the learned starter over the
+// wave, FP64 alpha, viscosity, collision, store.  Per-lane work is
+// predicated on `fl` so that the matrix-core section runs on whole waves.
+template <typename T, typename F, int C, bool LEARN>
+__global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W, int record) {
+  // thread-private LDS: populations of the current component (column p * BLK
+  // + tid) and, per wave, x_p (column p * 64 + lane), whose 9.5 KB also hold
+  // the starter's two [64][32] bf16 tiles before the alpha solve
   __shared__ T lds_f[NQ * BLK];
-  __shared__ double lds_x[NQ * BLK];
+  __shared__ __align__(16) double lds_x[NQ * BLK];
+  __shared__ __align__(16) LearnLds<LEARN> learn;
+  if constexpr (LEARN) mlp_stage(W, learn.net);
   Node nd;
   decode(a.boxes, a.block_box, nd);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   unsigned long long c_fb = 0, c_it = 0, c_neg = 0, c_nf = 0, c_col = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
-  if (nd.live && k == K_FLUID) {
+  const bool fl = nd.live && k == K_FLUID;
+  int nl[NQ];
+  unsigned solid = 0u;
+  F acc[C][3], wall[3] = {F(0), F(0), F(0)}, Fel[3] = {F(0), F(0), F(0)}, rt = F(1);
+#pragma unroll
+  for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
+  if (fl) {
     // ---- neighbours: local index, solid-or-outside flag
-    int nl[NQ];
-    unsigned solid = 0u;
     nl[0] = nd.n;
 #pragma unroll
     for (int p = 1; p < NQ; ++p) {
@@ -289,9 +317,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       if (nl[p] < 0 || (a.type[nd.B.off + nl[p]] & 3) == K_SOLID) solid |= 1u << p;
     }
     // ---- Shan-Chen (Eq. sc) and electric (Eq. force_el2) forces
-    F acc[C][3], wall[3] = {F(0), F(0), F(0)}, gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
-#pragma unroll
-    for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
+    F gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
     const F phic = a.phi[nd.g], e2c = a.e2[nd.g];
 #pragma unroll
     for (int p = 1; p < NQ; ++p) {
@@ -326,26 +352,28 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     }
     const F qn = a.q[nd.g];
     const F rA = a.rho[nd.g];
-    F Fel[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const F E = F(nd.B.E[d]) - gp[d] / F(CS2);
       Fel[d] = qn * E;
       if (M.electrostriction) Fel[d] += F(0.5) * rA * (ge[d] / F(CS2));
     }
-    F rt = F(0);
+    rt = F(0);
 #pragma unroll
     for (int s = 0; s < C; ++s) rt += a.rho[(int64_t)s * a.N + nd.g];
-    double mom[3] = {0.0, 0.0, 0.0}, drt = 0.0;
-    T *f = lds_f + threadIdx.x;
-    double *xs = lds_x + threadIdx.x;
+  }
+  double mom[3] = {0.0, 0.0, 0.0}, drt = 0.0;
+  T *f = lds_f + threadIdx.x;
+  double *xs = lds_x + wv * (NQ * 64) + lane;
 #pragma unroll
-    for (int s = 0; s < C; ++s) {
-      // ---- pulled populations and their moments.  The moments are summed
-      // in FP64 whatever the storage: the equilibrium of the alpha solve must
-      // carry exactly the density and momentum of f (sum Delta = 0), or the
-      // rounding of an FP32 sum swamps the O(|Delta|^2) entropy balance.
-      double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int s = 0; s < C; ++s) {
+    // ---- pulled populations and their moments.  The moments are summed in
+    // FP64 whatever the storage: the equilibrium of the alpha solve must carry
+    // exactly the density and momentum of f (sum Delta = 0), or the rounding
+    // of an FP32 sum swamps the O(|Delta|^2) entropy balance.
+    double dr = 1.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    if (fl) {
+      dr = 0.0;
 #pragma unroll
       for (int p = 0; p < NQ; ++p) {
         const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
@@ -359,6 +387,32 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
         jy += double(kCy[p]) * dv;
         jz += double(kCz[p]) * dv;
       }
+    }
+    const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+    // ---- alpha set-up at the component's own velocity (FP64)
+    AlphaSetup st{};
+    if (fl) st = alpha_setup<T>(f, xs, dr, ux, uy, uz, M.alpha_guess);
+    double a0 = 2.0;
+    if constexpr (LEARN) {
+      // ---- learned starter on the matrix cores, for waves holding a node
+      // where the series starter was rejected.  Its bf16 tiles overlay the
+      // wave's x scratch, which is refilled afterwards.
+      const bool want = fl && st.want_learned;
+      if (__ballot(want) != 0) {
+        float z[MLP_IN];
+        double sc = 0.0;
+        bool valid = false;
+        if (want) valid = features_from_x(xs, z, sc);
+        z[NQ] = float(sc);
+        wave_sync();
+        __bf16 *tile = reinterpret_cast<__bf16 *>(lds_x + wv * (NQ * 64));
+        put_features(tile, lane, z, valid);
+        const float y = mlp_forward_wave(learn.net, tile, tile + 64 * 32, lane);
+        if (valid) a0 = 2.0 + sc * double(y);
+        if (fl) refill_x<T>(f, xs, dr, ux, uy, uz);
+      }
+    }
+    if (fl) {
       drt += dr;
       const F ps = a.psi[(int64_t)s * a.N + nd.g];
       const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
@@ -368,12 +422,10 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       mom[0] += jx + 0.5 * double(Fs[0]);
       mom[1] += jy + 0.5 * double(Fs[1]);
       mom[2] += jz + 0.5 * double(Fs[2]);
-      // ---- alpha at the component's own velocity (FP64)
-      const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+      // ---- alpha: Newton polish from the starter
       const double uu = ux * ux + uy * uy + uz * uz;
       int its;
-      const double al = alpha_solve<T>(f, xs, dr, ux, uy, uz, M.alpha_guess == ELBM_GUESS_SERIES, M.rtol,
-                                       M.newton_max, its);
+      const double al = alpha_newton<T>(f, xs, st, a0, M.rtol, M.newton_max, its);
       c_col += 1;
       if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
       // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root,
@@ -422,11 +474,11 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
         a.rec_iters[(int64_t)s * a.N + nd.g] = its;
       }
     }
-    if (record) {
-      a.rec_u[nd.g] = F(mom[0] / drt);
-      a.rec_u[a.N + nd.g] = F(mom[1] / drt);
-      a.rec_u[2 * a.N + nd.g] = F(mom[2] / drt);
-    }
+  }
+  if (fl && record) {
+    a.rec_u[nd.g] = F(mom[0] / drt);
+    a.rec_u[a.N + nd.g] = F(mom[1] / drt);
+    a.rec_u[2 * a.N + nd.g] = F(mom[2] / drt);
   } else if (nd.live && record) {
     // boundary and wall nodes: populations stay; recorded velocity sum j / sum rho
     double r = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
@@ -457,7 +509,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
   c_neg = wave_sum_u64(c_neg);
   c_nf = wave_sum_u64(c_nf);
   c_col = wave_sum_u64(c_col);
-  if ((threadIdx.x & 63) == 0) {
+  if (lane == 0) {
     unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
     if (c_fb) atomicAdd(cn + 0, c_fb);
     if (c_it) atomicAdd(cn + 1, c_it);
@@ -467,6 +519,66 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       atomicOr(a.err, 1u);
     }
     if (c_col) atomicAdd(cn + 4, c_col);
+  }
+}
+
+// Training samples of the learned starter from the current state of one box:
+// for every fluid node and component, the starter input (z [19], s), the
+// target (alpha* - 2)/s with alpha* the plain Newton root from 2, the scale s
+// and a flag: 0 no features or the plain solve fell back, 1 a valid sample,
+// 2 a valid sample where the series starter is rejected (the nodes the
+// learned starter serves).  Outputs are indexed s * N_box + n.
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK) void k_alpha_samples(Ptrs<T, F> a, Model M, int box, float *feat,
+                                                       float *target, float *scale, int32_t *valid) {
+  __shared__ T lds_f[NQ * BLK];
+  __shared__ double lds_x[NQ * BLK];
+  Node nd;
+  decode(a.boxes, a.block_box, nd);
+  if (nd.bb != box || !nd.live) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool fl = (a.type[nd.g] & 3) == K_FLUID;
+  T *f = lds_f + threadIdx.x;
+  double *xs = lds_x + wv * (NQ * 64) + lane;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int64_t o = (int64_t)s * nd.B.n + nd.n;
+    bool ok = false, learned = false;
+    float z[NQ];
+    double sc = 0.0, al = 2.0;
+    if (fl) {
+      double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) {
+        const int q = opp(p);
+        const int m = p == 0 ? nd.n : nbr(nd.B, nd.x, nd.y, nd.z, kCx[q], kCy[q], kCz[q]);
+        const bool bounce = (p != 0) && (m < 0 || (a.type[nd.B.off + m] & 3) == K_SOLID);
+        const T v = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g]
+                           : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + m];
+        f[p * BLK] = v;
+        const double dv = double(v);
+        dr += dv;
+        jx += double(kCx[p]) * dv;
+        jy += double(kCy[p]) * dv;
+        jz += double(kCz[p]) * dv;
+      }
+      const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+      const AlphaSetup st = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_MLP);
+      ok = features_from_x(xs, z, sc);
+      learned = st.want_learned;
+      AlphaSetup plain = st;  // the target: Newton from 2
+      plain.a = 2.0;
+      plain.want_learned = false;
+      int its;
+      al = alpha_newton<T>(f, xs, plain, 2.0, M.rtol, M.newton_max, its);
+      ok = ok && its >= 0;
+    }
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) feat[o * MLP_IN + p] = ok ? z[p] : 0.0f;
+    feat[o * MLP_IN + NQ] = ok ? float(sc) : 0.0f;
+    target[o] = ok ? float((al - 2.0) / sc) : 0.0f;
+    scale[o] = ok ? float(sc) : 0.0f;
+    valid[o] = ok ? (learned ? 2 : 1) : 0;
   }
 }
 

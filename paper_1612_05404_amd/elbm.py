@@ -65,7 +65,8 @@ SYMBOLS = [
     "elbm_abi_version", "elbm_create", "elbm_required_bytes", "elbm_bind", "elbm_set_box", "elbm_step",
     "elbm_sync", "elbm_read_moments", "elbm_read_potential", "elbm_read_charge", "elbm_read_alpha",
     "elbm_get_populations", "elbm_set_populations", "elbm_set_potential", "elbm_diagnostics",
-    "elbm_set_graphs", "elbm_set_timing", "elbm_timing", "elbm_last_error", "elbm_destroy",
+    "elbm_set_graphs", "elbm_set_timing", "elbm_timing", "elbm_mlp_set_weights", "elbm_mlp_get_weights",
+    "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_train", "elbm_alpha_samples", "elbm_last_error", "elbm_destroy",
 ]
 PHASES = ["density", "charge", "poisson", "efield", "collide"]
 
@@ -98,6 +99,13 @@ def load(path: str = LIB_PATH):
     L.elbm_set_potential.argtypes = [vp, i32, vp]
     L.elbm_diagnostics.argtypes = [vp, i32, ct.POINTER(elbm_diag)]
     L.elbm_set_graphs.argtypes = [vp, i32]
+    i64, fp = ct.c_int64, ct.POINTER(ct.c_float)
+    L.elbm_mlp_set_weights.argtypes = [vp, vp, i64]
+    L.elbm_mlp_get_weights.argtypes = [vp, vp, i64]
+    L.elbm_mlp_forward.argtypes = [vp, vp, vp, i64]
+    L.elbm_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.elbm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ct.c_float, vp]
+    L.elbm_alpha_samples.argtypes = [vp, i32, vp, vp, vp, vp]
     L.elbm_set_timing.argtypes = [vp, i32]
     L.elbm_timing.argtypes = [vp, vp, vp]
     L.elbm_last_error.restype = ct.c_char_p
@@ -284,3 +292,70 @@ class Lattice:
         n = ct.c_int64()
         self._check(self.L.elbm_timing(self.h, ms.ctypes.data, ct.byref(n)))
         return dict(steps=n.value, **{k: float(v) for k, v in zip(PHASES, ms)})
+
+    # ---------------------------------------------------- learned starter
+    MLP_NPARAM = 1761
+    MLP_IN = 20
+
+    def mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.L.elbm_mlp_set_weights(self.h, w.ctypes.data, w.size))
+
+    def mlp_get_weights(self):
+        w = np.zeros(self.MLP_NPARAM, dtype=np.float32)
+        self._check(self.L.elbm_mlp_get_weights(self.h, w.ctypes.data, w.size))
+        return w
+
+    def mlp_forward(self, X):
+        """X: float32 device tensor [M, 20] -> float32 device tensor [M]."""
+        import torch
+        X = X.contiguous()
+        Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self.stream.wait_stream(torch.cuda.current_stream(X.device))
+        self._check(self.L.elbm_mlp_forward(self.h, ct.c_void_p(X.data_ptr()), ct.c_void_p(Y.data_ptr()),
+                                            X.shape[0]))
+        self.sync()
+        return Y
+
+    def mlp_grad(self, X, T):
+        """Gradient (FP32, parameter order) and loss of 1/(2M) sum (y - T)^2."""
+        import torch
+        X, T = X.contiguous(), T.contiguous()
+        g = np.zeros(self.MLP_NPARAM, dtype=np.float32)
+        loss = ct.c_float()
+        self.stream.wait_stream(torch.cuda.current_stream(X.device))
+        self._check(self.L.elbm_mlp_grad(self.h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()), X.shape[0],
+                                         g.ctypes.data, ct.byref(loss)))
+        return g, loss.value
+
+    def mlp_train(self, X, T, batch: int, steps: int, lr: float):
+        """Adam steps over consecutive batches of (X, T); returns the batch losses."""
+        import torch
+        X, T = X.contiguous(), T.contiguous()
+        self.stream.wait_stream(torch.cuda.current_stream(X.device))
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        done = 0
+        while done < steps:
+            n = min(4096, steps - done)
+            buf = np.zeros(n, dtype=np.float32)
+            self._check(self.L.elbm_mlp_train(self.h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()),
+                                              X.shape[0], int(batch), n, float(lr), buf.ctypes.data))
+            losses[done:done + n] = buf
+            done += n
+        return losses[:steps]
+
+    def alpha_samples(self, i: int = 0):
+        """Starter inputs (z, s) [C*N, 20], targets (alpha* - 2)/s [C*N],
+        scales s [C*N] and flags [C*N] (0 invalid, 1 valid, 2 valid and served
+        by the learned starter) of the current state of box i (device tensors)."""
+        import torch
+        b = self.boxes[i]
+        m = self.C * b.n
+        feat = torch.empty((m, self.MLP_IN), dtype=torch.float32, device=self.device)
+        tgt = torch.empty(m, dtype=torch.float32, device=self.device)
+        scl = torch.empty(m, dtype=torch.float32, device=self.device)
+        val = torch.empty(m, dtype=torch.int32, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.L.elbm_alpha_samples(self.h, i, ct.c_void_p(feat.data_ptr()), ct.c_void_p(tgt.data_ptr()),
+                                              ct.c_void_p(scl.data_ptr()), ct.c_void_p(val.data_ptr())))
+        return feat, tgt, scl, val
