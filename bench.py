@@ -10,8 +10,9 @@ forces, alpha, Carreau, collision) over the whole box.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second) over K
 steps replayed as captured step graphs, the roofline of the dominant kernel
-(the collision) from HIP events on the library's stream over the next K
-steps, and the CPU oracle timed on a bounded sample.
+(the collision, bound by FP64 arithmetic; its HBM roofline beside it) from
+HIP events on the library's stream over the next K steps, and the CPU oracle
+timed on a bounded sample.
 """
 import argparse
 import json
@@ -25,6 +26,17 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS coupled step, % of HBM roofline; learned-α vs plain Newton, same accuracy"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+COPY_MIB = 256
+
+# Counted with rocprofv3 --pmc on the default workload with the series
+# starter, over collision launches after the warm-up and the autotuner
+# (about step 250; early steps need more Newton updates): FP64 operations per
+# node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
+# instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
+# factors a plain 256 MiB copy gives for the same counters).
+COLLIDE_FP64_FLOP_PER_NODE = 21049
+COLLIDE_TRAFFIC_BYTES = 202_897_632
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -63,6 +75,48 @@ def cpu_baseline(wl, budget_s: float = 12.0, max_steps: int = 20):
                       f"{threads} OpenMP threads, {dt:.1f} s"}
 
 
+def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
+    """The batched ensemble: 256 independent periodic drop boxes (edges 24 to
+    64, own radius, charge, field and Carreau exponent), FP32 populations,
+    learned starter; the autotuner's trials serve as warm-up, then `steps`
+    steps replayed as captured graphs of the chosen mapping."""
+    import torch
+    t0 = time.perf_counter()
+    wl = inputs.ensemble()
+    mode = "mlp" if os.path.exists(learned.WEIGHTS) else "series"
+    print(f"[bench] ensemble: {len(wl.boxes)} boxes, {wl.nodes} nodes, guess {mode} "
+          f"(inputs {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
+    if mode == "mlp":
+        lat.mlp_set_weights(learned.load_weights())
+    best, ms = lat.autotune(trial)
+    lat.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(steps, record=False)
+    lat.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    lat.step(1, record=True)
+    diags = [lat.diagnostics(i) for i in range(len(wl.boxes))]
+    ncol = sum(d["n_collisions"] for d in diags)
+    iters = sum(d["mean_newton_iters"] * (d["n_collisions"] - d["n_fallback"]) for d in diags)
+    nfb = sum(d["n_fallback"] for d in diags)
+    lat.close()
+    edges = sorted({b.nx for b in wl.boxes})
+    return {
+        "workload": f"ensemble: {len(wl.boxes)} periodic drop boxes, edges {edges}, FP32 populations, FP64 alpha",
+        "nodes": wl.nodes,
+        "steps": steps,
+        "mlups": round(wl.nodes * steps / dt / 1e6, 3),
+        "ms_per_step": round(dt / steps * 1e3, 4),
+        "alpha_guess": mode,
+        "mean_newton_iters": round(iters / max(ncol - nfb, 1), 4),
+        "autotune": {"best": best, "ms_per_step": {f"remap{r}_graph{g}": round(float(ms[3 * r + k]), 4)
+                                                   for r in (0, 1) for k, g in enumerate((2, 4, 8))}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +128,8 @@ def main():
                     help="initial guess of the alpha Newton iteration for the reported value")
     ap.add_argument("--single-mode", action="store_true",
                     help="time only the reported guess (no comparison run)")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--ensemble-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -83,6 +139,14 @@ def main():
 
     import torch
     from paper_1612_05404_amd import elbm, inputs
+
+    # A plain device copy of known size (read + write of COPY_MIB each): the
+    # reference that scales HBM traffic counters taken over this program.
+    src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     wl = inputs.WORKLOADS[args.workload]()
     box = wl.boxes[0]
@@ -102,6 +166,7 @@ def main():
         if mode == "mlp":
             lat.mlp_set_weights(learned.load_weights())
         lat.step(args.warmup, record=False)
+        launch, _ = lat.autotune(16)
         lat.sync()
         # timed region: K steps as replayed step graphs, wall clock between
         # device-wide synchronisations
@@ -120,7 +185,7 @@ def main():
         # one recorded step for the solver statistics (outside the timed region)
         lat.step(1, record=True)
         diag = lat.diagnostics(0)
-        results[mode] = dict(dt=t1 - t0, ph=ph, diag=diag)
+        results[mode] = dict(dt=t1 - t0, ph=ph, diag=diag, launch=launch)
         lat.close()
         del lat
         torch.cuda.empty_cache()
@@ -133,6 +198,8 @@ def main():
     coll_ms = ph["collide"] / steps_timed
     cb = collide_bytes_per_node(esz, wl.params.ncomp)
     achieved = cb * nodes / (coll_ms * 1e-3) / 1e9
+    counted = wl.name == "efield_drop" and args.alpha_guess == "series"
+    tflops = COLLIDE_FP64_FLOP_PER_NODE * nodes / (coll_ms * 1e-3) / 1e12 if counted else None
     sb = step_bytes_per_node(esz, wl.params.ncomp, wl.params.sor_sweeps)
     comparison = {
         m: {"mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
@@ -161,15 +228,27 @@ def main():
             "sor_sweeps": wl.params.sor_sweeps,
             "alpha_guess": args.alpha_guess,
             "alpha_precision": "f64",
+            "launch": r["launch"],
         },
         "roofline": {
+            "kernel": "k_collide",
+            "bound": "alu",
+            "achieved": round(tflops, 3) if counted else None,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(tflops / FP64_PEAK_TFLOPS, 4) if counted else None,
+            "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
+            "fp64_flop_per_node": COLLIDE_FP64_FLOP_PER_NODE if counted else None,
+            "avg_ms": round(coll_ms, 5),
+        },
+        "roofline_hbm": {
             "kernel": "k_collide",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
             "bytes_per_node": cb,
             "avg_ms": round(coll_ms, 5),
         },
@@ -180,6 +259,8 @@ def main():
         "alpha_fallback_frac": round(diag["n_fallback"] / max(diag["n_collisions"], 1), 6),
         "alpha_guess_comparison": comparison,
     }
+    if not args.no_ensemble and args.workload == "efield_drop":
+        out["ensemble"] = ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

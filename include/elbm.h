@@ -237,6 +237,33 @@ elbm_status elbm_mlp_train(elbm_ctx *ctx, const void *dX, const void *dT, int64_
 elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dTarget, void *dScale,
                                void *dValid);
 
+/* ---- Launch mapping and its autotuner ----
+ * xcd_remap: 1 orders the node blocks so that each of the 8 XCDs runs one
+ * contiguous range of tiles (neighbouring tiles share an L2); 0 keeps the
+ * hardware's round-robin order.  graph_steps: steps captured in one HIP graph
+ * (even, 2..64).  Neither changes any result: per-node arithmetic and the
+ * order of every reduction are the same under both mappings. */
+typedef struct elbm_launch {
+  int32_t xcd_remap;
+  int32_t graph_steps;
+} elbm_launch;
+#define ELBM_TUNE_CANDIDATES 6
+/* Sets / reads the launch mapping (synchronises the bound stream; drops the
+ * captured graphs). */
+elbm_status elbm_set_launch(elbm_ctx *ctx, const elbm_launch *launch);
+elbm_status elbm_get_launch(const elbm_ctx *ctx, elbm_launch *launch);
+/* Times each of the ELBM_TUNE_CANDIDATES mappings (xcd_remap 0, 1 by
+ * graph_steps 2, 4, 8, in that order) over steps_per_trial steps (rounded up
+ * to a multiple of 16) with HIP events on the bound stream, in two rounds
+ * (forward, then reverse order; a candidate's time is its better round),
+ * keeps the fastest and returns it in best (may be NULL), with each
+ * candidate's ms per step in ms_per_step [ELBM_TUNE_CANDIDATES] (may be
+ * NULL).  The trial steps are ordinary steps: the state advances by
+ * 12 trial + 56 steps (each trial also runs one graph's worth of steps to
+ * capture it).
+ * Synchronous; phase timing must be off. */
+elbm_status elbm_autotune(elbm_ctx *ctx, int32_t steps_per_trial, elbm_launch *best, double *ms_per_step);
+
 /* Message of the last failing call on this context (never NULL). */
 const char *elbm_last_error(const elbm_ctx *ctx);
 

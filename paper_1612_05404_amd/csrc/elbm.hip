@@ -59,7 +59,10 @@ struct elbm_ctx {
   size_t ev_used = 0;
   double phase_ms[ELBM_NPHASES] = {0, 0, 0, 0, 0};
   int64_t timed_steps = 0;
-  // captured two-step graphs, indexed by the starting population parity
+  // launch mapping: XCD-aware block order, steps per captured graph (even)
+  int remap = 0;
+  int graph_steps = 2;
+  // captured step graphs, indexed by the starting population parity
   bool use_graphs = true;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   void drop_graphs() {
@@ -144,6 +147,8 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.cnt = (unsigned long long *)(b + c->o_cnt);
   a.err = (uint32_t *)(b + c->o_err);
   a.N = c->Ntot;
+  a.nblocks = c->nblocks;
+  a.remap = c->remap;
   return a;
 }
 
@@ -244,14 +249,15 @@ template <typename T, typename F, int C>
 elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
   int direct = nsteps;
   if (!c->timing && c->use_graphs && c->stream != nullptr) {
-    const int pairs = (record ? nsteps - 1 : nsteps) / 2;
+    const int k = c->graph_steps;  // even: a replay starts and ends at the same parity
+    const int pairs = (record ? nsteps - 1 : nsteps) / k;
     if (pairs > 0) {
       hipGraphExec_t &ge = c->graph_exec[c->parity];
       if (!ge) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        elbm_status s1 = enqueue_step<T, F, C>(c, 0);
-        elbm_status s2 = s1 ? s1 : enqueue_step<T, F, C>(c, 0);
+        elbm_status s2 = ELBM_OK;
+        for (int i = 0; i < k && !s2; ++i) s2 = enqueue_step<T, F, C>(c, 0);
         hipError_t ec = hipStreamEndCapture(c->stream, &g);
         if (s2) {
           if (g) (void)hipGraphDestroy(g);
@@ -266,7 +272,7 @@ elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
         }
       }
       for (int i = 0; i < pairs; ++i) HIPCHK(c, hipGraphLaunch(ge, c->stream));
-      direct = nsteps - 2 * pairs;
+      direct = nsteps - k * pairs;
     }
   }
   for (int it = 0; it < direct; ++it) {
@@ -543,6 +549,76 @@ elbm_status elbm_set_graphs(elbm_ctx *c, int32_t enable) {
   c->use_graphs = enable != 0;
   if (!c->use_graphs) c->drop_graphs();
   return ELBM_OK;
+}
+
+elbm_status elbm_set_launch(elbm_ctx *c, const elbm_launch *l) {
+  if (!c || !l) return ELBM_EINVAL;
+  if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(c, ELBM_EINVAL, "xcd_remap must be 0 or 1");
+  if (l->graph_steps < 2 || l->graph_steps > 64 || (l->graph_steps & 1))
+    return fail(c, ELBM_EINVAL, "graph_steps must be even, 2..64");
+  if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->remap = l->xcd_remap;
+  c->graph_steps = l->graph_steps;
+  c->drop_graphs();  // kernel arguments and step counts are baked into the graphs
+  return ELBM_OK;
+}
+
+elbm_status elbm_get_launch(const elbm_ctx *c, elbm_launch *l) {
+  if (!c || !l) return ELBM_EINVAL;
+  l->xcd_remap = c->remap;
+  l->graph_steps = c->graph_steps;
+  return ELBM_OK;
+}
+
+elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *best, double *ms_per_step) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (c->timing) return fail(c, ELBM_ESTATE, "autotune with phase timing on");
+  if (steps_per_trial < 1) return fail(c, ELBM_EINVAL, "steps_per_trial must be >= 1");
+  const int trial = (steps_per_trial + 15) / 16 * 16;  // whole replays of every candidate
+  static const int kSteps[3] = {2, 4, 8};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  elbm_launch keep{c->remap, c->graph_steps}, win = keep;
+  double best_ms = INFINITY, per_cand[ELBM_TUNE_CANDIDATES];
+  for (double &v : per_cand) v = INFINITY;
+  elbm_status st = ELBM_OK;
+  // two rounds, forward then reverse order, best per candidate: a state that
+  // drifts during the trials (an initial transient) favours no candidate
+  for (int t = 0; t < 2 * ELBM_TUNE_CANDIDATES && !st; ++t) {
+    const int cand = t < ELBM_TUNE_CANDIDATES ? t : 2 * ELBM_TUNE_CANDIDATES - 1 - t;
+    const elbm_launch l{cand / 3, kSteps[cand % 3]};
+    st = elbm_set_launch(c, &l);
+    if (!st) st = elbm_step(c, l.graph_steps, 0);  // captures the graph
+    if (st) break;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, ELBM_EHIP, "hipEventRecord"); break; }
+    st = elbm_step(c, trial, 0);
+    if (st) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(c, ELBM_EHIP, "autotune timing");
+      break;
+    }
+    per_cand[cand] = fmin(per_cand[cand], ms / trial);
+  }
+  for (int cand = 0; cand < ELBM_TUNE_CANDIDATES && !st; ++cand) {
+    if (ms_per_step) ms_per_step[cand] = per_cand[cand];
+    if (per_cand[cand] < best_ms) {
+      best_ms = per_cand[cand];
+      win = elbm_launch{cand / 3, kSteps[cand % 3]};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    (void)elbm_set_launch(c, &keep);
+    return st;
+  }
+  st = elbm_set_launch(c, &win);
+  if (!st && best) *best = win;
+  return st;
 }
 
 elbm_status elbm_sync(elbm_ctx *c) {

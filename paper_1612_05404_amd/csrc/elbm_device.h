@@ -66,21 +66,35 @@ struct Ptrs {
   unsigned long long *cnt;  // [nboxes][NCNT]
   uint32_t *err;
   int64_t N;            // arena nodes (plane stride)
+  int32_t nblocks;      // node blocks of one launch
+  int32_t remap;        // 1: XCD-aware block order
 };
 
 // ------------------------------------------------------------ node decode
 struct Node {
   BoxDev B;
-  int bb;
+  int bb, blk;  // box, logical block
   int64_t g;
   int n, x, y, z;
   bool live;
 };
 
-__device__ __forceinline__ void decode(const BoxDev *boxes, const int32_t *block_box, Node &nd) {
-  nd.bb = block_box[blockIdx.x];
-  nd.B = boxes[nd.bb];
-  nd.g = (int64_t)blockIdx.x * BLK + threadIdx.x;
+// Logical block of this workgroup.  Workgroups go to the 8 XCDs round-robin;
+// with remap, XCD k runs one contiguous range of logical blocks, so tiles
+// that share halos share an L2.  A bijection of [0, nb).
+__device__ __forceinline__ int logical_block(int nb, int remap) {
+  const int b = blockIdx.x;
+  if (!remap) return b;
+  const int q = nb >> 3, r = nb & 7, k = b & 7, i = b >> 3;
+  return (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + i;
+}
+
+template <typename P>
+__device__ __forceinline__ void decode(const P &a, Node &nd) {
+  nd.blk = logical_block(a.nblocks, a.remap);
+  nd.bb = a.block_box[nd.blk];
+  nd.B = a.boxes[nd.bb];
+  nd.g = (int64_t)nd.blk * BLK + threadIdx.x;
   nd.n = (int)(nd.g - nd.B.off);
   nd.live = nd.n < nd.B.n;
   const int t = nd.live ? nd.n : 0;

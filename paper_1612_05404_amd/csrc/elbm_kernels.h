@@ -27,7 +27,7 @@ namespace elbm {
 template <typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live) return;
   const int k = a.type[nd.g] & 3;
   int src[NQ];
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live) return;
   F g0 = F(0), g1 = F(0), g2 = F(0);
   if ((a.type[nd.g] & 3) != K_SOLID) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (nd.live) {
     const uint8_t tt = a.type[nd.g];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
       acc[3] = surf;
     }
   }
-  block_sum_store<4>(acc, a.partials + (int64_t)blockIdx.x * 4);
+  block_sum_store<4>(acc, a.partials + (int64_t)nd.blk * 4);
 }
 
 // One block per box: deterministic fixed-order sum of the box's block
@@ -176,7 +176,7 @@ __constant__ int kFace[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live) return;
   const double *sc = a.scal + (int64_t)nd.bb * NSCAL;
   const uint8_t tt = a.type[nd.g];
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live) return;
   if (((nd.x + nd.y + nd.z) & 1) != colour) return;
   if (a.type[nd.g] & B_DIRICHLET) return;
@@ -222,9 +222,9 @@ __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   double acc[1] = {nd.live ? double(a.phi[nd.g]) : 0.0};
-  block_sum_store<1>(acc, a.partials + (int64_t)blockIdx.x * 4);
+  block_sum_store<1>(acc, a.partials + (int64_t)nd.blk * 4);
 }
 
 __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const double *partials,
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const dou
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live || nd.B.has_dirichlet) return;
   a.phi[nd.g] -= F(a.scal[(int64_t)nd.bb * NSCAL + 3]);
 }
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (!nd.live) return;
   const F c = a.phi[nd.g];
   F g0 = F(0), g1 = F(0), g2 = F(0);
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W
   __shared__ __align__(16) LearnLds<LEARN> learn;
   if constexpr (LEARN) mlp_stage(W, learn.net);
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   unsigned long long c_fb = 0, c_it = 0, c_neg = 0, c_nf = 0, c_col = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(BLK) void k_alpha_samples(Ptrs<T, F> a, Model M, in
   __shared__ T lds_f[NQ * BLK];
   __shared__ double lds_x[NQ * BLK];
   Node nd;
-  decode(a.boxes, a.block_box, nd);
+  decode(a, nd);
   if (nd.bb != box || !nd.live) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool fl = (a.type[nd.g] & 3) == K_FLUID;

@@ -51,6 +51,10 @@ class elbm_box(ct.Structure):
     ]
 
 
+class elbm_launch(ct.Structure):
+    _fields_ = [("xcd_remap", ct.c_int32), ("graph_steps", ct.c_int32)]
+
+
 class elbm_diag(ct.Structure):
     _fields_ = [
         ("mass", ct.c_double * 2), ("momentum", ct.c_double * 3),
@@ -66,8 +70,10 @@ SYMBOLS = [
     "elbm_sync", "elbm_read_moments", "elbm_read_potential", "elbm_read_charge", "elbm_read_alpha",
     "elbm_get_populations", "elbm_set_populations", "elbm_set_potential", "elbm_diagnostics",
     "elbm_set_graphs", "elbm_set_timing", "elbm_timing", "elbm_mlp_set_weights", "elbm_mlp_get_weights",
-    "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_train", "elbm_alpha_samples", "elbm_last_error", "elbm_destroy",
+    "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_train", "elbm_alpha_samples", "elbm_set_launch",
+    "elbm_get_launch", "elbm_autotune", "elbm_last_error", "elbm_destroy",
 ]
+TUNE_CANDIDATES = 6
 PHASES = ["density", "charge", "poisson", "efield", "collide"]
 
 _lib = None
@@ -106,6 +112,9 @@ def load(path: str = LIB_PATH):
     L.elbm_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
     L.elbm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ct.c_float, vp]
     L.elbm_alpha_samples.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.elbm_set_launch.argtypes = [vp, ct.POINTER(elbm_launch)]
+    L.elbm_get_launch.argtypes = [vp, ct.POINTER(elbm_launch)]
+    L.elbm_autotune.argtypes = [vp, i32, ct.POINTER(elbm_launch), vp]
     L.elbm_set_timing.argtypes = [vp, i32]
     L.elbm_timing.argtypes = [vp, vp, vp]
     L.elbm_last_error.restype = ct.c_char_p
@@ -359,3 +368,24 @@ class Lattice:
         self._check(self.L.elbm_alpha_samples(self.h, i, ct.c_void_p(feat.data_ptr()), ct.c_void_p(tgt.data_ptr()),
                                               ct.c_void_p(scl.data_ptr()), ct.c_void_p(val.data_ptr())))
         return feat, tgt, scl, val
+
+    # ---------------------------------------------------- launch mapping
+    def set_launch(self, xcd_remap: int, graph_steps: int):
+        self._check(self.L.elbm_set_launch(self.h, ct.byref(elbm_launch(int(xcd_remap), int(graph_steps)))))
+
+    def get_launch(self) -> dict:
+        l = elbm_launch()
+        self._check(self.L.elbm_get_launch(self.h, ct.byref(l)))
+        return {"xcd_remap": l.xcd_remap, "graph_steps": l.graph_steps}
+
+    def autotune(self, steps_per_trial: int = 32):
+        """Times the launch mappings (two interleaved rounds), keeps the
+        fastest; returns it and the per-candidate ms per step (xcd_remap 0, 1
+        by graph_steps 2, 4, 8).  The trial steps advance the state like
+        ordinary steps (12 trials + 56 in all)."""
+        import torch
+        best = elbm_launch()
+        ms = np.zeros(TUNE_CANDIDATES)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.L.elbm_autotune(self.h, int(steps_per_trial), ct.byref(best), ms.ctypes.data))
+        return {"xcd_remap": best.xcd_remap, "graph_steps": best.graph_steps}, ms

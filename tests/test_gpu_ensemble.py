@@ -1,0 +1,117 @@
+"""Batched ensembles: uneven droplet boxes advanced together in one launch per
+phase (captured step graphs), against single-box runs, the CPU oracle and
+every launch mapping the autotuner chooses from."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1612_05404_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def elbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1612_05404_amd import elbm as E
+    E.load()
+    return E
+
+
+def _fields(lat, i):
+    rho, u = lat.read_moments(i)
+    return rho, u, lat.read_potential(i), lat.read_charge(i)
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_ensemble_equals_single_box_runs(elbm):
+    # Every box of a batched run must be bit-identical to the same box run
+    # alone: per-box parameters, per-box reductions, no cross-box coupling.
+    wl = inputs.ensemble(nboxes=6, edges=(24, 32))
+    _say(f"[gpu ensemble] 6 boxes {[b.nx for b in wl.boxes]} f32, 24 steps, batched vs alone")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+    lat.step(24, record=True)
+    for i, b in enumerate(wl.boxes):
+        one = elbm.Lattice(wl.params, [b], "f32")
+        one.step(24, record=True)
+        assert _same(_fields(lat, i), _fields(one, 0)), f"box {i} differs"
+        d_all, d_one = lat.diagnostics(i), one.diagnostics(0)
+        assert d_all["mean_newton_iters"] == d_one["mean_newton_iters"]
+        one.close()
+    lat.close()
+
+
+def test_launch_mappings_give_identical_results(elbm):
+    # XCD-aware block order and longer graphs change scheduling only.
+    wl = inputs.ensemble(nboxes=5, edges=(24, 32, 48))
+    _say("[gpu ensemble] launch mappings, 5 boxes f32, 24 steps")
+    ref = None
+    for remap, gs in ((0, 2), (1, 2), (0, 8), (1, 4)):
+        lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+        lat.set_launch(remap, gs)
+        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs}
+        lat.step(24, record=True)
+        got = [_fields(lat, i) for i in range(len(wl.boxes))]
+        if ref is None:
+            ref = got
+        else:
+            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs)
+        lat.close()
+    with pytest.raises(elbm.ElbmError):
+        lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+        try:
+            lat.set_launch(0, 3)
+        finally:
+            lat.close()
+
+
+def test_ensemble_fp64_matches_oracle(elbm):
+    # Three boxes with their own field, charge, Carreau exponent and SOR
+    # factor, FP64, against the oracle box by box at the FP64 bar.
+    import oracle as ora
+    from test_gpu_parity import compare
+    wl = inputs.ensemble(nboxes=3, edges=(24,))
+    _say("[gpu ensemble] 3 boxes 24^3 f64 vs oracle, 30 steps")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f64")
+    lat.set_launch(1, 4)
+    lat.step(30, record=True)
+    for i, b in enumerate(wl.boxes):
+        o = ora.Oracle(wl.params, b, nthreads=NTHREADS)
+        o.step(30)
+        _say(f"    box {i}: E_z {b.info['E_ext'][2]:.2e} Q_b {b.info['Q_b']:.3e} n {b.info['n_flow']:.3f}")
+        compare(lat, i, o, 1e-12)
+    lat.close()
+
+
+def test_autotune_keeps_results(elbm):
+    # The autotuner times all mappings, keeps the fastest and leaves the
+    # state where the same number of plain steps leaves it.
+    wl = inputs.ensemble(nboxes=4, edges=(24, 32))
+    _say("[gpu ensemble] autotune, 4 boxes f32")
+    a = elbm.Lattice(wl.params, wl.boxes, "f32")
+    best, ms = a.autotune(16)
+    _say(f"    best {best}; ms/step per candidate {np.round(ms, 4).tolist()}")
+    assert np.all(np.isfinite(ms)) and np.all(ms > 0)
+    assert best == a.get_launch()
+    assert ms[3 * best["xcd_remap"] + {2: 0, 4: 1, 8: 2}[best["graph_steps"]]] == ms.min()
+    b = elbm.Lattice(wl.params, wl.boxes, "f32")
+    b.step(12 * 16 + 56, record=False)
+    a.step(1, record=True)
+    b.step(1, record=True)
+    for i in range(len(wl.boxes)):
+        assert _same(_fields(a, i), _fields(b, i)), i
+    a.close()
+    b.close()
