@@ -240,7 +240,12 @@ __device__ __forceinline__ double phi_of(double y, double l) {
 // learned starter (ELBM_GUESS_MLP) takes the series starter where it is
 // accepted and the network's a0 where it is not (and a0 lies in the
 // positivity interval).  Every starter is polished by Newton to the same
-// stopping rule.  The update count goes to `iters`, or -1 with the fallback
+// stopping rule.  At an accepted series root b the rule can hold without an
+// evaluation of g: with q the truncated series, g(b)/b - q(b) is the series
+// tail from degree 8, bounded by b^7 M_8 / (56 (1 - b max|x|)) for
+// b max|x| < 1, and S(b) >= b^2 M_2 (1 - b max|x|/3) / 2 (phi(y) >= y^2/2 -
+// |y|^3/6).  When b (|q(b)| + tail) <= rtol S_lower / 2, the evaluation would
+// accept b with 0 updates, so b is returned directly.  The update count goes to `iters`, or -1 with the fallback
 // min(2, 0.99 a_max) when there is no root, Newton does not converge, or a
 // population is not positive (H undefined).
 // f: the node's 19 populations of one component (thread-private LDS column,
@@ -253,17 +258,17 @@ constexpr double SERIES_ACCEPT = 1.2;
 // State between the set-up pass and the Newton polish.
 struct AlphaSetup {
   double L, amax, xmax, a;  // a: the starter so far
-  int state;                // 0: Newton needed, 1: done (a, iters 0), 2: fallback
+  int state;                // 0: Newton needed, 1: at equilibrium (2), 2: fallback, 3: the rule holds at a
   bool want_learned;        // the learned starter would be used here
 };
 
 template <typename T>
 __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double rho, double ux, double uy,
-                                                  double uz, int guess) {
+                                                  double uz, int guess, double rtol) {
   const double uu = ux * ux + uy * uy + uz * uz;
   const double irho = rcp_nr(rho);
   double xmax = 0.0, amax = INFINITY, L = 0.0;
-  double M2 = 0.0, M3 = 0.0, M4 = 0.0, M5 = 0.0, M6 = 0.0, M7 = 0.0;
+  double M2 = 0.0, M3 = 0.0, M4 = 0.0, M5 = 0.0, M6 = 0.0, M7 = 0.0, M8 = 0.0;
   bool nonpos = false;
 #pragma unroll 4
   for (int p = 0; p < NQ; ++p) {
@@ -286,7 +291,9 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
     M5 += t;
     t *= x;
     M6 += t;
-    M7 += t * x;
+    t *= x;
+    M7 += t;
+    M8 += t * x;
   }
   AlphaSetup st;
   st.L = L;
@@ -313,24 +320,35 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
       if (!(dq > 0.0)) break;
       b -= q / dq;
     }
-    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) st.a = b;
-    else st.want_learned = guess == ELBM_GUESS_MLP;
+    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
+      st.a = b;
+      const double bx = b * xmax;
+      if (bx < 0.5) {
+        const double qb = L + b * (M2 / 2.0 + b * (-M3 / 6.0 + b * (M4 / 12.0 + b * (-M5 / 20.0 + b * (M6 / 30.0 - b * M7 / 42.0)))));
+        const double b3 = b * b * b;
+        const double tail = b3 * b3 * b * M8 / (56.0 * (1.0 - bx));
+        if (b * (fabs(qb) + tail) <= 0.25 * rtol * b * b * M2 * (1.0 - bx / 3.0)) st.state = 3;
+      }
+    } else {
+      st.want_learned = guess == ELBM_GUESS_MLP;
+    }
   }
   return st;
 }
 
+// Newton's starting point for a node that needs the iteration (state 0).
+__device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
+  double a = st.a;
+  if (st.want_learned && a0 > 0.0 && a0 < st.amax) a = a0;
+  if (!(a > 0.0 && a < st.amax)) a = 0.5 * fmin(st.amax, 4.0);
+  return a;
+}
+
+// Newton on g from a inside (0, amax) (f, xs as for the set-up pass).
 template <typename T>
-__device__ __forceinline__ double alpha_newton(const T *f, const double *xs, AlphaSetup st, double a0, double rtol,
-                                               int maxit, int &iters) {
-  if (st.state == 1) {
-    iters = 0;
-    return 2.0;
-  }
-  if (st.state == 0) {
-    double a = st.a;
-    if (st.want_learned && a0 > 0.0 && a0 < st.amax) a = a0;
-    if (!(a > 0.0 && a < st.amax)) a = 0.5 * fmin(st.amax, 4.0);
-    const double L = st.L, amax = st.amax;
+__device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double a,
+                                                double rtol, int maxit, int &iters) {
+  {
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L;
 #pragma unroll 4
@@ -358,6 +376,18 @@ __device__ __forceinline__ double alpha_newton(const T *f, const double *xs, Alp
       a = an;
     }
   }
+  iters = -1;
+  return fmin(2.0, 0.99 * amax);
+}
+
+template <typename T>
+__device__ __forceinline__ double alpha_newton(const T *f, const double *xs, AlphaSetup st, double a0, double rtol,
+                                               int maxit, int &iters) {
+  if (st.state == 1 || st.state == 3) {
+    iters = 0;
+    return st.state == 1 ? 2.0 : st.a;
+  }
+  if (st.state == 0) return alpha_iterate<T>(f, xs, st.L, st.amax, alpha_start(st, a0), rtol, maxit, iters);
   iters = -1;
   return fmin(2.0, 0.99 * st.amax);
 }

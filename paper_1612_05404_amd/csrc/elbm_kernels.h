@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
     // ---- alpha set-up at the component's own velocity (FP64)
     AlphaSetup st{};
-    if (fl) st = alpha_setup<T>(f, xs, dr, ux, uy, uz, M.alpha_guess);
+    if (fl) st = alpha_setup<T>(f, xs, dr, ux, uy, uz, M.alpha_guess, M.rtol);
     double a0 = 2.0;
     if constexpr (LEARN) {
       // ---- learned starter on the matrix cores, for waves holding a node
@@ -563,13 +563,10 @@ __global__ __launch_bounds__(BLK) void k_alpha_samples(Ptrs<T, F> a, Model M, in
         jz += double(kCz[p]) * dv;
       }
       const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
-      const AlphaSetup st = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_MLP);
+      learned = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_MLP, M.rtol).want_learned;
       ok = features_from_x(xs, z, sc);
-      learned = st.want_learned;
-      AlphaSetup plain = st;  // the target: Newton from 2
-      plain.a = 2.0;
-      plain.want_learned = false;
-      int its;
+      const AlphaSetup plain = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_STANDARD, M.rtol);
+      int its;  // the target: Newton from 2
       al = alpha_newton<T>(f, xs, plain, 2.0, M.rtol, M.newton_max, its);
       ok = ok && its >= 0;
     }
