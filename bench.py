@@ -35,8 +35,8 @@ COPY_MIB = 256
 # node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
 # instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
 # factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 21049
-COLLIDE_TRAFFIC_BYTES = 202_897_632
+COLLIDE_FP64_FLOP_PER_NODE = 19764
+COLLIDE_TRAFFIC_BYTES = 202_929_118
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:

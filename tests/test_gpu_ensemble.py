@@ -96,6 +96,32 @@ def test_ensemble_fp64_matches_oracle(elbm):
     lat.close()
 
 
+def test_full_ensemble_sampled(elbm):
+    # The full 256-box ensemble (27.5 M nodes, FP32) in the launch mapping the
+    # autotuner picks for it (XCD-aware order, 2-step graphs), 8 steps: the
+    # smallest and largest boxes equal the same boxes run alone bit for bit,
+    # and the first 24^3 box matches the FP64 oracle at the FP32 bar.
+    import oracle as ora
+    from test_gpu_parity import compare
+    wl = inputs.ensemble()
+    edges = [b.nx for b in wl.boxes]
+    i24, i64 = edges.index(24), edges.index(64)
+    _say(f"[gpu ensemble] full: {len(wl.boxes)} boxes, {wl.nodes} nodes, 8 steps; sampled boxes {i24}, {i64}")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+    lat.set_launch(1, 2)
+    lat.step(8, record=True)
+    lat.sync()
+    for i in (i24, i64):
+        one = elbm.Lattice(wl.params, [wl.boxes[i]], "f32")
+        one.step(8, record=True)
+        assert _same(_fields(lat, i), _fields(one, 0)), f"box {i} differs"
+        one.close()
+    o = ora.Oracle(wl.params, wl.boxes[i24], nthreads=NTHREADS)
+    o.step(8)
+    compare(lat, i24, o, 1e-5)
+    lat.close()
+
+
 def test_autotune_keeps_results(elbm):
     # The autotuner times all mappings, keeps the fastest and leaves the
     # state where the same number of plain steps leaves it.

@@ -204,6 +204,27 @@ def test_jet_geometry_small_fp64(elbm):
     compare(lat, 0, o, 1e-12)
 
 
+def test_jet_full_size_fp32(elbm):
+    # The jet at its full size (128x128x512, FP32 populations, Carreau, inlet
+    # disk, outlet plane, electrodes, generator charge) in a tuned launch
+    # mapping (XCD-aware order, 8-step graphs), 3 steps against the FP64
+    # oracle on every node at the FP32 bar.
+    import oracle as ora
+    wl = inputs.jet()
+    b = wl.boxes[0]
+    _say(f"[gpu parity] jet {b.nx}x{b.ny}x{b.nz} f32, 3 steps, launch (1, 8)")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+    lat.set_launch(1, 8)
+    lat.step(3, record=True)
+    lat.sync()
+    o = ora.Oracle(wl.params, b, nthreads=NTHREADS)
+    o.step(3)
+    compare(lat, 0, o, 1e-5)
+    d = lat.diagnostics(0)
+    _say(f"    diag: collisions {d['n_collisions']} fallbacks {d['n_fallback']} negative {d['n_negative']}")
+    assert d["n_collisions"] > 0
+
+
 def test_conservation_and_checkpoint(elbm):
     # Periodic FP64 drop: each component's mass is constant to rounding, and
     # get/set of the populations + potential resumes bit-exactly.
