@@ -245,7 +245,11 @@ __device__ __forceinline__ double phi_of(double y, double l) {
 // tail from degree 8, bounded by b^7 M_8 / (56 (1 - b max|x|)) for
 // b max|x| < 1, and S(b) >= b^2 M_2 (1 - b max|x|/3) / 2 (phi(y) >= y^2/2 -
 // |y|^3/6).  When b (|q(b)| + tail) <= rtol S_lower / 2, the evaluation would
-// accept b with 0 updates, so b is returned directly.  The update count goes to `iters`, or -1 with the fallback
+// accept b with 0 updates, so b is returned directly.  Likewise after a plain
+// Newton step d from a: by Taylor, |g(a + d)| <= g''_max d^2 / 2 with
+// g'' = sum f x^2 / (1 + xi x) <= M_2 / D, D = 1 - max(a, a + d) / a_max, and
+// S(a + d) >= S(a) - |d| max(a, a + d) M_2 / D; within half the tolerance the
+// evaluation at a + d would accept it, so it is returned without one.  The update count goes to `iters`, or -1 with the fallback
 // min(2, 0.99 a_max) when there is no root, Newton does not converge, or a
 // population is not positive (H undefined).
 // f: the node's 19 populations of one component (thread-private LDS column,
@@ -258,6 +262,7 @@ constexpr double SERIES_ACCEPT = 1.2;
 // State between the set-up pass and the Newton polish.
 struct AlphaSetup {
   double L, amax, xmax, a;  // a: the starter so far
+  double M2;                // sum_p f_p x_p^2
   int state;                // 0: Newton needed, 1: at equilibrium (2), 2: fallback, 3: the rule holds at a
   bool want_learned;        // the learned starter would be used here
 };
@@ -296,6 +301,7 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
     M8 += t * x;
   }
   AlphaSetup st;
+  st.M2 = M2;
   st.L = L;
   st.amax = amax;
   st.xmax = xmax;
@@ -346,8 +352,8 @@ __device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
 
 // Newton on g from a inside (0, amax) (f, xs as for the set-up pass).
 template <typename T>
-__device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double a,
-                                                double rtol, int maxit, int &iters) {
+__device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double M2,
+                                                double a, double rtol, int maxit, int &iters) {
   {
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L;
@@ -367,11 +373,22 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
       }
       if (it == maxit) break;
       double an = (gp > 0.0) ? a - g / gp : 2.0 * a;
+      const bool newton = gp > 0.0 && an > 0.0 && an < amax;
       if (an >= amax) an = 0.5 * (a + amax);
       if (an <= 0.0) an = 0.5 * a;
       if (fabs(an - a) <= 4.0 * 2.220446049250313e-16 * a) {
         iters = it + 1;
         return an;
+      }
+      if (newton) {  // Taylor bound at the Newton point (see above)
+        const double d = an - a, hi = fmax(a, an), D = 1.0 - hi / amax;
+        if (D > 0.0) {
+          const double G2 = M2 / D;
+          if (G2 * d * d <= rtol * (S - fabs(d) * hi * G2)) {
+            iters = it + 1;
+            return an;
+          }
+        }
       }
       a = an;
     }
@@ -387,7 +404,7 @@ __device__ __forceinline__ double alpha_newton(const T *f, const double *xs, Alp
     iters = 0;
     return st.state == 1 ? 2.0 : st.a;
   }
-  if (st.state == 0) return alpha_iterate<T>(f, xs, st.L, st.amax, alpha_start(st, a0), rtol, maxit, iters);
+  if (st.state == 0) return alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), rtol, maxit, iters);
   iters = -1;
   return fmin(2.0, 0.99 * st.amax);
 }
