@@ -35,8 +35,8 @@ COPY_MIB = 256
 # node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
 # instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
 # factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 19764
-COLLIDE_TRAFFIC_BYTES = 202_929_118
+COLLIDE_FP64_FLOP_PER_NODE = 18300
+COLLIDE_TRAFFIC_BYTES = 202_878_613
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -117,6 +117,45 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
     }
 
 
+def jet_leg(elbm, inputs, learned, warmup: int, steps: int):
+    """The jet (128x128x512, FP32, inlet disk and collector, Carreau, generator
+    charge): after `warmup` steps and the autotuner, `steps` graph-replayed
+    steps with each starter; MLUPS and mean Newton updates at identical alpha."""
+    import torch
+    t0 = time.perf_counter()
+    wl = inputs.jet()
+    b = wl.boxes[0]
+    print(f"[bench] jet {b.nx}x{b.ny}x{b.nz} (inputs {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    out = {"workload": f"jet: {b.nx}x{b.ny}x{b.nz}, inlet disk r 8, E_z 2e-3, Carreau n 0.4, FP32 populations, "
+                       f"FP64 alpha, {wl.params.sor_sweeps} SOR sweeps/step",
+           "nodes": wl.nodes, "warmup": warmup, "steps": steps, "starters": {}}
+    for mode in ("standard", "series", "mlp"):
+        if mode == "mlp" and not os.path.exists(learned.WEIGHTS):
+            continue
+        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
+        if mode == "mlp":
+            lat.mlp_set_weights(learned.load_weights())
+        lat.step(warmup, record=False)
+        launch, _ = lat.autotune(16)
+        lat.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.step(steps, record=False)
+        lat.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        lat.step(1, record=True)
+        d = lat.diagnostics(0)
+        out["starters"][mode] = {"mlups": round(wl.nodes * steps / dt / 1e6, 3),
+                                 "mean_newton_iters": round(d["mean_newton_iters"], 4),
+                                 "fallback_frac": round(d["n_fallback"] / max(d["n_collisions"], 1), 6),
+                                 "launch": launch}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +169,9 @@ def main():
                     help="time only the reported guess (no comparison run)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--ensemble-steps", type=int, default=100)
+    ap.add_argument("--no-jet", action="store_true", help="skip the jet leg (three starters)")
+    ap.add_argument("--jet-warmup", type=int, default=200)
+    ap.add_argument("--jet-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -261,6 +303,8 @@ def main():
     }
     if not args.no_ensemble and args.workload == "efield_drop":
         out["ensemble"] = ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32)
+    if not args.no_jet and args.workload == "efield_drop":
+        out["jet"] = jet_leg(elbm, inputs, learned, args.jet_warmup, args.jet_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
