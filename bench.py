@@ -35,8 +35,8 @@ COPY_MIB = 256
 # node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
 # instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
 # factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 18300
-COLLIDE_TRAFFIC_BYTES = 202_878_613
+COLLIDE_FP64_FLOP_PER_NODE = 17648
+COLLIDE_TRAFFIC_BYTES = 203_363_605
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
