@@ -189,6 +189,17 @@ def test_efield_full_size_fp32(elbm):
     check_fp32(lat, o, wl.params, wl.boxes[0], 100)
 
 
+@pytest.mark.parametrize("curvature,electrostriction", [(0, 1), (1, 0), (0, 0)])
+def test_term_switches_fp64(elbm, curvature, electrostriction):
+    # The curvature weight of the surface charge and the electrostriction force
+    # switched off one at a time and together, FP64, against the oracle.
+    p = inputs.base_params(Q_b=0.03, Q_s=0.3, E_ext=[0.0, 0.0, 1e-3], sor_sweeps=6, sor_omega=1.5,
+                           curvature=curvature, electrostriction=electrostriction)
+    b = inputs.droplet_box(16, 16, 24, 5.0, seed=31)
+    lat, (o,) = run_both(elbm, p, [b], "f64", 60, f"switches curvature={curvature} electrostriction={electrostriction}")
+    compare(lat, 0, o, 1e-12)
+
+
 def test_single_component_fp64(elbm):
     # The paper's own model: one Shan-Chen fluid, G = -5, liquid 1.93 / vapour 0.156.
     b = inputs.droplet_box(16, 16, 16, 5.0, seed=21, ncomp=1, rho_in=1.93, rho_out=0.156)

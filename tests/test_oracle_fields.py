@@ -3,6 +3,7 @@ invariants, gradient and curvature stencils, charge normalisation, Poisson
 solver, Shan-Chen force and conservation over many steps.  Each expected
 value comes from numpy/scipy routines, closed forms or brute force."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -272,6 +273,35 @@ def test_shan_chen_single_component_coexistence(ora):
     r = o.field(ora.F_RHO)[0, :, 0, 0]
     assert abs(r[32] - rl) / rl < 5e-3, (r[32], rl)
     assert abs(r[0] - rg) / rg < 1.5e-2, (r[0], rg)  # lattice accuracy of the gas branch
+
+
+@pytest.mark.slow
+def test_laplace_law_single_component(ora):
+    # A drop at rest (one component, G = -5, no charge): the pressure jump from
+    # the Shan-Chen equation of state p = c_s^2 (rho + G psi^2 / 2) scales as
+    # 1/R (Laplace, 2 sigma / R in 3-D).  R is the equilibrium radius from the
+    # liquid volume.  The liquid density also falls toward the flat-interface
+    # coexistence value as R grows.
+    G = -5.0
+    p = inputs.Params(ncomp=1, G=[[G, 0.0], [0.0, 0.0]], Q_b=0.0, Q_s=0.0, sor_sweeps=0, sor_omega=1.5)
+    rows = []
+    for R, n in ((8, 32), (10, 32), (12, 40)):
+        b = inputs.droplet_box(n, n, n, R, seed=5, ncomp=1, rho_in=1.93, rho_out=0.156)
+        o = ora.Oracle(p, b, nthreads=min(16, os.cpu_count() or 1))
+        o.step(600)
+        rho = o.field(ora.F_RHO)[0]
+        pres = (rho + 0.5 * G * (1.0 - np.exp(-rho)) ** 2) / 3.0
+        c = slice(n // 2 - 1, n // 2 + 1)
+        rl, rg = rho[c, c, c].mean(), rho[:2, :2, :2].mean()
+        dp = pres[c, c, c].mean() - pres[:2, :2, :2].mean()
+        r_eq = (3.0 * ((rho - rg) / (rl - rg)).sum() / (4.0 * math.pi)) ** (1.0 / 3.0)
+        rows.append((r_eq, dp, rl))
+    two_sigma = np.array([dp * r for r, dp, _ in rows])
+    assert np.all([dp > 0 for _, dp, _ in rows])
+    assert np.ptp(two_sigma) / two_sigma.mean() < 0.04, two_sigma
+    assert rows[0][1] > rows[1][1] > rows[2][1]
+    rl_flat, _ = _sc_coexistence_theory(G)
+    assert rows[0][2] > rows[1][2] > rows[2][2] > rl_flat
 
 
 def test_shan_chen_critical_coupling(ora):
