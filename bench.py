@@ -9,10 +9,14 @@ update (pull, densities, curvature and charge, Poisson, electric field,
 forces, alpha, Carreau, collision) over the whole box.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second) over K
-steps replayed as captured step graphs, the roofline of the dominant kernel
-(the collision, bound by FP64 arithmetic; its HBM roofline beside it) from
-HIP events on the library's stream over the next K steps, and the CPU oracle
-timed on a bounded sample.
+steps (default 2000, the whole configured run, after W warm-up steps from the
+initial state) replayed as captured step graphs, in the launch mapping the
+autotuner chose on a separate instance; the per-phase breakdown of the same
+W + K steps from HIP events on the library's stream (second instance); the
+roofline of the dominant kernel (the collision, bound by FP64 arithmetic; its
+HBM roofline beside it) from its event-timed launches over steps 251..266,
+the window its hardware counters are taken on (third instance); and the CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -28,15 +32,16 @@ METRIC = "MLUPS coupled step, % of HBM roofline; learned-α vs plain Newton, sam
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 COPY_MIB = 256
+ROOF_AT, ROOF_STEPS = 250, 16  # the collision's roofline window: steps 251..266
 
 # Counted with rocprofv3 --pmc on the default workload with the series
-# starter, over collision launches after the warm-up and the autotuner
-# (about step 250; early steps need more Newton updates): FP64 operations per
+# starter and the autotuner's mapping, over the collision launches of steps
+# 251..266 (early steps need more Newton updates): FP64 operations per
 # node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
 # instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
 # factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 17648
-COLLIDE_TRAFFIC_BYTES = 203_363_605
+COLLIDE_FP64_FLOP_PER_NODE = 16120
+COLLIDE_TRAFFIC_BYTES = 1_042_623_066
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -112,8 +117,10 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
         "ms_per_step": round(dt / steps * 1e3, 4),
         "alpha_guess": mode,
         "mean_newton_iters": round(iters / max(ncol - nfb, 1), 4),
-        "autotune": {"best": best, "ms_per_step": {f"remap{r}_graph{g}": round(float(ms[3 * r + k]), 4)
-                                                   for r in (0, 1) for k, g in enumerate((2, 4, 8))}},
+        "autotune": {"best": best, "ms_per_step": dict(
+            [(f"tile{t}", round(float(ms[t]), 4)) for t in range(4)]
+            + [(f"remap{r}", round(float(ms[4 + r]), 4)) for r in range(2)]
+            + [(f"graph{g}", round(float(ms[6 + k]), 4)) for k, g in enumerate((2, 4, 8))])},
     }
 
 
@@ -159,7 +166,8 @@ def jet_leg(elbm, inputs, learned, warmup: int, steps: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000,
+                    help="timed steps (default: the field drop's configured run length)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -172,6 +180,9 @@ def main():
     ap.add_argument("--no-jet", action="store_true", help="skip the jet leg (three starters)")
     ap.add_argument("--jet-warmup", type=int, default=200)
     ap.add_argument("--jet-steps", type=int, default=100)
+    ap.add_argument("--launch", default=None, help="launch mapping remap,graph_steps,tile (skips the autotuner)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the collision's roofline window (for counter runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -200,36 +211,74 @@ def main():
         sys.exit(f"--alpha-guess mlp needs the stored network {learned.WEIGHTS}")
     modes = [args.alpha_guess] + [m for m in ("standard", "series", "mlp")
                                   if m != args.alpha_guess and (m != "mlp" or have_net)]
+    def make(mode, launch=None):
+        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
+        if mode == "mlp":
+            lat.mlp_set_weights(learned.load_weights())
+        if launch:
+            lat.set_launch(**launch)
+        return lat
+
+    def tuned_launch(mode):
+        if args.launch:
+            r, g, t = (int(v) for v in args.launch.split(","))
+            return {"xcd_remap": r, "graph_steps": g, "tile": t}
+        # tuned on a throw-away instance: the timed runs start from the initial state
+        lat = make(mode)
+        lat.step(args.warmup, record=False)
+        launch, _ = lat.autotune(32)
+        lat.close()
+        return launch
+
+    def roofline_window(mode, launch):
+        # collision time over the window where the counters are taken
+        lat = make(mode, launch)
+        lat.step(ROOF_AT, record=False)
+        lat.set_timing(True)
+        lat.step(ROOF_STEPS, record=False)
+        ph = lat.timing()
+        lat.close()
+        return ph["collide"] / max(ph["steps"], 1)
+
+    if args.roofline_only:
+        launch = tuned_launch(args.alpha_guess)
+        ms = roofline_window(args.alpha_guess, launch)
+        print(json.dumps({"roofline_window": {"steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS], "collide_ms": round(ms, 5),
+                                              "launch": launch}}), flush=True)
+        return
+
     results = {}
     for mode in modes:
         print(f"[bench] workload {wl.name} {box.nx}x{box.ny}x{box.nz} dtype {wl.dtype} sor_sweeps "
               f"{wl.params.sor_sweeps} alpha guess {mode}", file=sys.stderr, flush=True)
-        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
-        if mode == "mlp":
-            lat.mlp_set_weights(learned.load_weights())
+        launch = tuned_launch(mode)
+        # timed region: W warm-up steps, then K steps as replayed step graphs,
+        # wall clock between device-wide synchronisations
+        lat = make(mode, launch)
         lat.step(args.warmup, record=False)
-        launch, _ = lat.autotune(16)
         lat.sync()
-        # timed region: K steps as replayed step graphs, wall clock between
-        # device-wide synchronisations
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat.step(args.steps, record=False)
         lat.sync()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        # the next K steps with HIP events around every phase (direct
-        # launches) for the per-kernel durations of the roofline
-        lat.set_timing(True)
-        lat.step(args.steps, record=False)
-        ph = lat.timing()
-        lat.set_timing(False)
         # one recorded step for the solver statistics (outside the timed region)
         lat.step(1, record=True)
         diag = lat.diagnostics(0)
-        results[mode] = dict(dt=t1 - t0, ph=ph, diag=diag, launch=launch)
         lat.close()
-        del lat
+        res = dict(dt=t1 - t0, diag=diag, launch=launch)
+        if mode == args.alpha_guess:
+            # the same W + K steps again with HIP events around every phase
+            # (direct launches): the per-phase breakdown of the timed run
+            lat = make(mode, launch)
+            lat.step(args.warmup, record=False)
+            lat.set_timing(True)
+            lat.step(args.steps, record=False)
+            res["ph"] = lat.timing()
+            lat.close()
+            res["roof_ms"] = roofline_window(mode, launch)
+        results[mode] = res
         torch.cuda.empty_cache()
         if args.single_mode:
             break
@@ -237,7 +286,7 @@ def main():
     dt, ph, diag = r["dt"], r["ph"], r["diag"]
     mlups = nodes * args.steps / dt / 1e6
     steps_timed = max(ph["steps"], 1)
-    coll_ms = ph["collide"] / steps_timed
+    coll_ms = r["roof_ms"]
     cb = collide_bytes_per_node(esz, wl.params.ncomp)
     achieved = cb * nodes / (coll_ms * 1e-3) / 1e9
     counted = wl.name == "efield_drop" and args.alpha_guess == "series"
@@ -245,8 +294,8 @@ def main():
     sb = step_bytes_per_node(esz, wl.params.ncomp, wl.params.sor_sweeps)
     comparison = {
         m: {"mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
-            "collide_ms": round(v["ph"]["collide"] / max(v["ph"]["steps"], 1), 5),
-            "mean_newton_iters": round(v["diag"]["mean_newton_iters"], 4)}
+            "mean_newton_iters": round(v["diag"]["mean_newton_iters"], 4),
+            "launch": v["launch"]}
         for m, v in results.items()
     }
     out = {
@@ -282,6 +331,7 @@ def main():
             "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
             "fp64_flop_per_node": COLLIDE_FP64_FLOP_PER_NODE if counted else None,
             "avg_ms": round(coll_ms, 5),
+            "window_steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS],
         },
         "roofline_hbm": {
             "kernel": "k_collide",

@@ -241,26 +241,32 @@ elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dT
  * xcd_remap: 1 orders the node blocks so that each of the 8 XCDs runs one
  * contiguous range of tiles (neighbouring tiles share an L2); 0 keeps the
  * hardware's round-robin order.  graph_steps: steps captured in one HIP graph
- * (even, 2..64).  Neither changes any result: per-node arithmetic and the
- * order of every reduction are the same under both mappings. */
+ * (even, 2..64).  tile: the collision's block tile, 0 = 256 consecutive nodes
+ * (a 64-thread wave is a run along x), 1 = 8x8x4 nodes (waves 8x8x1),
+ * 2 = 8x4x8 (waves 8x4x2), 3 = 4x4x16 (waves 4x4x4): 3-D waves gather the
+ * nodes whose alpha needs many Newton updates (at interfaces) into fewer
+ * waves.  None changes any result: per-node arithmetic and the order of
+ * every reduction are the same under all mappings. */
 typedef struct elbm_launch {
   int32_t xcd_remap;
   int32_t graph_steps;
+  int32_t tile;
 } elbm_launch;
-#define ELBM_TUNE_CANDIDATES 6
+#define ELBM_TUNE_CANDIDATES 9
 /* Sets / reads the launch mapping (synchronises the bound stream; drops the
  * captured graphs). */
 elbm_status elbm_set_launch(elbm_ctx *ctx, const elbm_launch *launch);
 elbm_status elbm_get_launch(const elbm_ctx *ctx, elbm_launch *launch);
-/* Times each of the ELBM_TUNE_CANDIDATES mappings (xcd_remap 0, 1 by
- * graph_steps 2, 4, 8, in that order) over steps_per_trial steps (rounded up
- * to a multiple of 16) with HIP events on the bound stream, in two rounds
- * (forward, then reverse order; a candidate's time is its better round),
- * keeps the fastest and returns it in best (may be NULL), with each
- * candidate's ms per step in ms_per_step [ELBM_TUNE_CANDIDATES] (may be
- * NULL).  The trial steps are ordinary steps: the state advances by
- * 12 trial + 56 steps (each trial also runs one graph's worth of steps to
- * capture it).
+/* Chooses the mapping in three passes, each timing its candidates over
+ * steps_per_trial steps (rounded up to a multiple of 16) with HIP events on
+ * the bound stream, in two rounds (forward, then reverse order; a
+ * candidate's time is the mean of its two rounds), and keeping the fastest for the
+ * next pass: tile 0..3 (with xcd_remap 0, graph_steps 2), then xcd_remap
+ * 0, 1, then graph_steps 2, 4, 8.  best (may be NULL) receives the result;
+ * ms_per_step [ELBM_TUNE_CANDIDATES] (may be NULL) each candidate's ms per
+ * step in that order.  The trial steps are ordinary steps: the state
+ * advances by 18 trial + 52 steps (each of the 18 trials first runs one
+ * graph's worth of steps to capture it).
  * Synchronous; phase timing must be off. */
 elbm_status elbm_autotune(elbm_ctx *ctx, int32_t steps_per_trial, elbm_launch *best, double *ms_per_step);
 

@@ -59,9 +59,16 @@ struct elbm_ctx {
   size_t ev_used = 0;
   double phase_ms[ELBM_NPHASES] = {0, 0, 0, 0, 0};
   int64_t timed_steps = 0;
-  // launch mapping: XCD-aware block order, steps per captured graph (even)
+  // launch mapping: XCD-aware block order, steps per captured graph (even),
+  // block tile shape of the collision (0: linear)
   int remap = 0;
   int graph_steps = 2;
+  int tile = 0;
+  // per tile shape: tile -> box table, per-box tile counts, tiles in all
+  std::vector<int32_t> tile_box[NTILE_SHAPES];
+  std::vector<int4> box_tiles[NTILE_SHAPES];
+  int ntiles[NTILE_SHAPES] = {0, 0, 0, 0};
+  size_t o_tbox[NTILE_SHAPES] = {0, 0, 0, 0}, o_btiles[NTILE_SHAPES] = {0, 0, 0, 0};
   // captured step graphs, indexed by the starting population parity
   bool use_graphs = true;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -149,6 +156,12 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.N = c->Ntot;
   a.nblocks = c->nblocks;
   a.remap = c->remap;
+  a.tile_box = (const int32_t *)(b + c->o_tbox[c->tile]);
+  a.box_tiles = (const int4 *)(b + c->o_btiles[c->tile]);
+  a.tx = tile_dim(c->tile, 0);
+  a.ty = tile_dim(c->tile, 1);
+  a.tz = tile_dim(c->tile, 2);
+  a.ntiles = c->ntiles[c->tile];
   return a;
 }
 
@@ -231,10 +244,11 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   mark(c, ev, 3);
   hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 4);
+  const dim3 cgrid(c->tile ? (unsigned)c->ntiles[c->tile] : grid.x);
   if (M.alpha_guess == ELBM_GUESS_MLP)
-    hipLaunchKernelGGL((k_collide<T, F, C, true>), grid, blk, 0, c->stream, a, M, make_mlp(c), rec);
+    hipLaunchKernelGGL((k_collide<T, F, C, true>), cgrid, blk, 0, c->stream, a, M, make_mlp(c), rec);
   else
-    hipLaunchKernelGGL((k_collide<T, F, C, false>), grid, blk, 0, c->stream, a, M, make_mlp(c), rec);
+    hipLaunchKernelGGL((k_collide<T, F, C, false>), cgrid, blk, 0, c->stream, a, M, make_mlp(c), rec);
   mark(c, ev, 5);
   c->parity ^= 1;
   HIPCHK(c, hipGetLastError());
@@ -442,6 +456,19 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   }
   c->Ntot = off;
   c->nblocks = blk0;
+  for (int s = 1; s < NTILE_SHAPES; ++s) {
+    int t0 = 0;
+    for (int b = 0; b < nboxes; ++b) {
+      const elbm_box &x = boxes[b];
+      const int ntx = (x.nx + tile_dim(s, 0) - 1) / tile_dim(s, 0), nty = (x.ny + tile_dim(s, 1) - 1) / tile_dim(s, 1),
+                ntz = (x.nz + tile_dim(s, 2) - 1) / tile_dim(s, 2);
+      c->box_tiles[s].push_back(int4{t0, ntx, nty, ntz});
+      const int nt = ntx * nty * ntz;
+      for (int i = 0; i < nt; ++i) c->tile_box[s].push_back(b);
+      t0 += nt;
+    }
+    c->ntiles[s] = t0;
+  }
   const int C = P->ncomp;
   const int64_t N = c->Ntot;
   const size_t e = c->esz_fld, ep = c->esz_pop;
@@ -478,6 +505,10 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_mgrad = take(sizeof(float) * (MLP_NPARAM + 1));
   c->o_mpart = take(sizeof(float) * MLP_GGRID * MLP_GRAD_SLOTS);
   c->o_mloss = take(sizeof(float) * MLP_MAX_STEPS);
+  for (int s = 1; s < NTILE_SHAPES; ++s) {
+    c->o_tbox[s] = take(sizeof(int32_t) * c->tile_box[s].size());
+    c->o_btiles[s] = take(sizeof(int4) * c->box_tiles[s].size());
+  }
   c->total = o;
   *out = c;
   return ELBM_OK;
@@ -507,6 +538,14 @@ elbm_status elbm_bind(elbm_ctx *c, void *arena, size_t bytes, void *stream) {
   HIPCHK(c, hipMemset(c->base, 0, c->o_type));
   HIPCHK(c, hipMemset(c->base + c->o_type, K_SOLID, (size_t)c->Ntot));
   HIPCHK(c, hipMemset(c->base + c->o_scal, 0, c->total - c->o_scal));
+  // the collision's tile tables live past the cleared region's start: upload after the clear
+  for (int s = 1; s < NTILE_SHAPES; ++s) {
+    HIPCHK(c, hipMemcpy(c->base + c->o_tbox[s], c->tile_box[s].data(), sizeof(int32_t) * c->tile_box[s].size(),
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->base + c->o_btiles[s], c->box_tiles[s].data(), sizeof(int4) * c->box_tiles[s].size(),
+                        hipMemcpyHostToDevice));
+  }
+
   c->bound = true;
   return ELBM_OK;
 }
@@ -556,9 +595,11 @@ elbm_status elbm_set_launch(elbm_ctx *c, const elbm_launch *l) {
   if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(c, ELBM_EINVAL, "xcd_remap must be 0 or 1");
   if (l->graph_steps < 2 || l->graph_steps > 64 || (l->graph_steps & 1))
     return fail(c, ELBM_EINVAL, "graph_steps must be even, 2..64");
+  if (l->tile < 0 || l->tile >= NTILE_SHAPES) return fail(c, ELBM_EINVAL, "tile must be 0..3");
   if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
   c->remap = l->xcd_remap;
   c->graph_steps = l->graph_steps;
+  c->tile = l->tile;
   c->drop_graphs();  // kernel arguments and step counts are baked into the graphs
   return ELBM_OK;
 }
@@ -567,6 +608,25 @@ elbm_status elbm_get_launch(const elbm_ctx *c, elbm_launch *l) {
   if (!c || !l) return ELBM_EINVAL;
   l->xcd_remap = c->remap;
   l->graph_steps = c->graph_steps;
+  l->tile = c->tile;
+  return ELBM_OK;
+}
+
+// Times one launch mapping over `trial` steps (after the steps that capture
+// its graph); ms per step into *ms.
+static elbm_status time_launch(elbm_ctx *c, const elbm_launch &l, int trial, hipEvent_t e0, hipEvent_t e1,
+                               double *ms) {
+  elbm_status st = elbm_set_launch(c, &l);
+  if (!st) st = elbm_step(c, l.graph_steps, 0);
+  if (st) return st;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, ELBM_EHIP, "hipEventRecord");
+  st = elbm_step(c, trial, 0);
+  if (st) return st;
+  float t = 0.f;
+  if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+    return fail(c, ELBM_EHIP, "autotune timing");
+  *ms = t / trial;
   return ELBM_OK;
 }
 
@@ -576,39 +636,43 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
   if (c->timing) return fail(c, ELBM_ESTATE, "autotune with phase timing on");
   if (steps_per_trial < 1) return fail(c, ELBM_EINVAL, "steps_per_trial must be >= 1");
   const int trial = (steps_per_trial + 15) / 16 * 16;  // whole replays of every candidate
-  static const int kSteps[3] = {2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  elbm_launch keep{c->remap, c->graph_steps}, win = keep;
-  double best_ms = INFINITY, per_cand[ELBM_TUNE_CANDIDATES];
-  for (double &v : per_cand) v = INFINITY;
+  const elbm_launch keep{c->remap, c->graph_steps, c->tile};
+  elbm_launch cur{0, 2, 0};
   elbm_status st = ELBM_OK;
-  // two rounds, forward then reverse order, best per candidate: a state that
-  // drifts during the trials (an initial transient) favours no candidate
-  for (int t = 0; t < 2 * ELBM_TUNE_CANDIDATES && !st; ++t) {
-    const int cand = t < ELBM_TUNE_CANDIDATES ? t : 2 * ELBM_TUNE_CANDIDATES - 1 - t;
-    const elbm_launch l{cand / 3, kSteps[cand % 3]};
-    st = elbm_set_launch(c, &l);
-    if (!st) st = elbm_step(c, l.graph_steps, 0);  // captures the graph
-    if (st) break;
-    if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, ELBM_EHIP, "hipEventRecord"); break; }
-    st = elbm_step(c, trial, 0);
-    if (st) break;
-    float ms = 0.f;
-    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = fail(c, ELBM_EHIP, "autotune timing");
-      break;
+  // three passes, each fixing one knob with the winners of the earlier ones:
+  // tile shape (4), XCD order (2), graph length (3); within a pass two
+  // rounds, forward then reverse order, and a candidate's time is the mean of
+  // its two: a state that drifts linearly during the trials (an initial
+  // transient) then favours no candidate
+  static const int kSteps[3] = {2, 4, 8};
+  int slot = 0;
+  for (int pass = 0; pass < 3 && !st; ++pass) {
+    const int n = pass == 0 ? NTILE_SHAPES : pass == 1 ? 2 : 3;
+    double per[NTILE_SHAPES];
+    for (int k = 0; k < n; ++k) per[k] = 0.0;
+    for (int t = 0; t < 2 * n && !st; ++t) {
+      const int k = t < n ? t : 2 * n - 1 - t;
+      elbm_launch l = cur;
+      if (pass == 0) l.tile = k;
+      else if (pass == 1) l.xcd_remap = k;
+      else l.graph_steps = kSteps[k];
+      double ms = 0.0;
+      st = time_launch(c, l, trial, e0, e1, &ms);
+      if (!st) per[k] += 0.5 * ms;
     }
-    per_cand[cand] = fmin(per_cand[cand], ms / trial);
-  }
-  for (int cand = 0; cand < ELBM_TUNE_CANDIDATES && !st; ++cand) {
-    if (ms_per_step) ms_per_step[cand] = per_cand[cand];
-    if (per_cand[cand] < best_ms) {
-      best_ms = per_cand[cand];
-      win = elbm_launch{cand / 3, kSteps[cand % 3]};
+    if (st) break;
+    int kb = 0;
+    for (int k = 0; k < n; ++k) {
+      if (ms_per_step) ms_per_step[slot + k] = per[k];
+      if (per[k] < per[kb]) kb = k;
     }
+    slot += n;
+    if (pass == 0) cur.tile = kb;
+    else if (pass == 1) cur.xcd_remap = kb;
+    else cur.graph_steps = kSteps[kb];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -616,8 +680,8 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
     (void)elbm_set_launch(c, &keep);
     return st;
   }
-  st = elbm_set_launch(c, &win);
-  if (!st && best) *best = win;
+  st = elbm_set_launch(c, &cur);
+  if (!st && best) *best = cur;
   return st;
 }
 

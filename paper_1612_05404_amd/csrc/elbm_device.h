@@ -68,7 +68,21 @@ struct Ptrs {
   int64_t N;            // arena nodes (plane stride)
   int32_t nblocks;      // node blocks of one launch
   int32_t remap;        // 1: XCD-aware block order
+  // block tiles of the collision (tx = 0: 256 consecutive nodes per block)
+  const int32_t *tile_box;  // [ntiles] box of each tile
+  const int4 *box_tiles;    // [nboxes] first tile, tiles along x, y, z
+  int32_t tx, ty, tz, ntiles;
 };
+
+// Block tile shapes of the collision, index 1..: the 256 threads cover
+// tx x ty x tz nodes, x fastest, so each 64-thread wave is a 3-D patch
+// (8x8x1, 8x4x2, 4x4x4); index 0 is the linear mapping.
+constexpr int NTILE_SHAPES = 4;
+__host__ __device__ constexpr int tile_dim(int shape, int axis) {
+  return shape == 1 ? (axis == 0 ? 8 : axis == 1 ? 8 : 4)
+       : shape == 2 ? (axis == 0 ? 8 : axis == 1 ? 4 : 8)
+       : shape == 3 ? (axis == 0 ? 4 : axis == 1 ? 4 : 16) : 0;
+}
 
 // ------------------------------------------------------------ node decode
 struct Node {
@@ -87,6 +101,26 @@ __device__ __forceinline__ int logical_block(int nb, int remap) {
   if (!remap) return b;
   const int q = nb >> 3, r = nb & 7, k = b & 7, i = b >> 3;
   return (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + i;
+}
+
+// Node of this thread in the tiled mapping (a.tx > 0).  Threads of a tile
+// beyond the box edge are not live (their coordinates are the tile corner's).
+template <typename P>
+__device__ __forceinline__ void decode_tile(const P &a, Node &nd) {
+  nd.blk = logical_block(a.ntiles, a.remap);
+  nd.bb = a.tile_box[nd.blk];
+  nd.B = a.boxes[nd.bb];
+  const int4 bt = a.box_tiles[nd.bb];
+  const int lt = nd.blk - bt.x;
+  const int bx = lt % bt.y, r = lt / bt.y, by = r % bt.z, bz = r / bt.z;
+  const int t = threadIdx.x, r2 = t / a.tx;
+  const int x = bx * a.tx + t % a.tx, y = by * a.ty + r2 % a.ty, z = bz * a.tz + r2 / a.ty;
+  nd.live = x < nd.B.nx && y < nd.B.ny && z < nd.B.nz;
+  nd.x = nd.live ? x : bx * a.tx;
+  nd.y = nd.live ? y : by * a.ty;
+  nd.z = nd.live ? z : bz * a.tz;
+  nd.n = nd.x + nd.B.nx * (nd.y + nd.B.ny * nd.z);
+  nd.g = nd.B.off + nd.n;
 }
 
 template <typename P>

@@ -310,7 +310,8 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W
   __shared__ __align__(16) LearnLds<LEARN> learn;
   if constexpr (LEARN) mlp_stage(W, learn.net);
   Node nd;
-  decode(a, nd);
+  if (a.tx) decode_tile(a, nd);
+  else decode(a, nd);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   unsigned long long c_fb = 0, c_it = 0, c_neg = 0, c_nf = 0, c_col = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;

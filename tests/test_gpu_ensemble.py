@@ -59,23 +59,24 @@ def test_launch_mappings_give_identical_results(elbm):
     wl = inputs.ensemble(nboxes=5, edges=(24, 32, 48))
     _say("[gpu ensemble] launch mappings, 5 boxes f32, 24 steps")
     ref = None
-    for remap, gs in ((0, 2), (1, 2), (0, 8), (1, 4)):
+    for remap, gs, tile in ((0, 2, 0), (1, 2, 0), (0, 8, 1), (1, 4, 2), (0, 2, 3), (1, 8, 3)):
         lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-        lat.set_launch(remap, gs)
-        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs}
+        lat.set_launch(remap, gs, tile)
+        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs, "tile": tile}
         lat.step(24, record=True)
-        got = [_fields(lat, i) for i in range(len(wl.boxes))]
+        got = [_fields(lat, i) + (lat.read_alpha(i)[0],) for i in range(len(wl.boxes))]
         if ref is None:
             ref = got
         else:
-            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs)
+            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs, tile)
         lat.close()
-    with pytest.raises(elbm.ElbmError):
-        lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-        try:
-            lat.set_launch(0, 3)
-        finally:
-            lat.close()
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32")
+    try:
+        for bad in ((0, 3, 0), (2, 2, 0), (0, 2, 4)):
+            with pytest.raises(elbm.ElbmError):
+                lat.set_launch(*bad)
+    finally:
+        lat.close()
 
 
 def test_ensemble_fp64_matches_oracle(elbm):
@@ -86,7 +87,7 @@ def test_ensemble_fp64_matches_oracle(elbm):
     wl = inputs.ensemble(nboxes=3, edges=(24,))
     _say("[gpu ensemble] 3 boxes 24^3 f64 vs oracle, 30 steps")
     lat = elbm.Lattice(wl.params, wl.boxes, "f64")
-    lat.set_launch(1, 4)
+    lat.set_launch(1, 4, 3)
     lat.step(30, record=True)
     for i, b in enumerate(wl.boxes):
         o = ora.Oracle(wl.params, b, nthreads=NTHREADS)
@@ -108,7 +109,7 @@ def test_full_ensemble_sampled(elbm):
     i24, i64 = edges.index(24), edges.index(64)
     _say(f"[gpu ensemble] full: {len(wl.boxes)} boxes, {wl.nodes} nodes, 8 steps; sampled boxes {i24}, {i64}")
     lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-    lat.set_launch(1, 2)
+    lat.set_launch(1, 2, 1)
     lat.step(8, record=True)
     lat.sync()
     for i in (i24, i64):
@@ -132,9 +133,12 @@ def test_autotune_keeps_results(elbm):
     _say(f"    best {best}; ms/step per candidate {np.round(ms, 4).tolist()}")
     assert np.all(np.isfinite(ms)) and np.all(ms > 0)
     assert best == a.get_launch()
-    assert ms[3 * best["xcd_remap"] + {2: 0, 4: 1, 8: 2}[best["graph_steps"]]] == ms.min()
+    # passes: tile 0..3, then XCD order 0..1, then graph length 2, 4, 8
+    assert ms[best["tile"]] == ms[:4].min()
+    assert ms[4 + best["xcd_remap"]] == ms[4:6].min()
+    assert ms[6 + {2: 0, 4: 1, 8: 2}[best["graph_steps"]]] == ms[6:].min()
     b = elbm.Lattice(wl.params, wl.boxes, "f32")
-    b.step(12 * 16 + 56, record=False)
+    b.step(18 * 16 + 52, record=False)
     a.step(1, record=True)
     b.step(1, record=True)
     for i in range(len(wl.boxes)):

@@ -218,14 +218,14 @@ def test_jet_geometry_small_fp64(elbm):
 def test_jet_full_size_fp32(elbm):
     # The jet at its full size (128x128x512, FP32 populations, Carreau, inlet
     # disk, outlet plane, electrodes, generator charge) in a tuned launch
-    # mapping (XCD-aware order, 8-step graphs), 3 steps against the FP64
+    # mapping (XCD-aware order, 8-step graphs, 8x8x4 collision tiles), 3 steps against the FP64
     # oracle on every node at the FP32 bar.
     import oracle as ora
     wl = inputs.jet()
     b = wl.boxes[0]
-    _say(f"[gpu parity] jet {b.nx}x{b.ny}x{b.nz} f32, 3 steps, launch (1, 8)")
+    _say(f"[gpu parity] jet {b.nx}x{b.ny}x{b.nz} f32, 3 steps, launch (remap 1, graph 8, tile 8x8x4)")
     lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-    lat.set_launch(1, 8)
+    lat.set_launch(1, 8, 1)
     lat.step(3, record=True)
     lat.sync()
     o = ora.Oracle(wl.params, b, nthreads=NTHREADS)
