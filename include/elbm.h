@@ -82,7 +82,9 @@ typedef struct {
     int32_t alpha_guess;      /* ELBM_GUESS_*                                       */
     int32_t pad_;
     double G[2][2];           /* Shan-Chen couplings G[s][s'] (Eq. sc)              */
-    double Gw;                /* fluid-wall coupling (Eq. sc)                       */
+    double Gw[2][2];          /* fluid-wall couplings Gw[s][s'] (Eq. sc, wall sum): a wall
+                                 neighbour carries the node's own psi^s'; Gw = G is a
+                                 neutral wall                                       */
     double nu0, nu_inf, lam;  /* viscosity (Newtonian: nu0), Carreau nu_inf, lambda */
     double K_d;               /* curvature doubling the surface charge              */
     double rho_th, w_theta;   /* smoothed Heaviside: 0.5(1+tanh((rho-rho_th)/w))    */

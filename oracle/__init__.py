@@ -39,7 +39,7 @@ class OraParams(ct.Structure):
         ("charge_model", ct.c_int32),
         ("sor_sweeps", ct.c_int32), ("newton_max", ct.c_int32), ("nthreads", ct.c_int32),
         ("pad_", ct.c_int32),
-        ("G", (ct.c_double * 2) * 2), ("Gw", ct.c_double),
+        ("G", (ct.c_double * 2) * 2), ("Gw", (ct.c_double * 2) * 2),
         ("nu0", ct.c_double), ("nu_inf", ct.c_double), ("lam", ct.c_double), ("n_flow", ct.c_double),
         ("Q_b", ct.c_double), ("Q_s", ct.c_double), ("xi_b", ct.c_double), ("xi_s", ct.c_double),
         ("K_d", ct.c_double), ("rho_th", ct.c_double), ("w_theta", ct.c_double),
@@ -137,11 +137,12 @@ def make_params(p, box, nthreads: int = 0) -> OraParams:
     P.carreau, P.curvature, P.electrostriction = int(p.carreau), int(p.curvature), int(p.electrostriction)
     P.charge_model = int(p.charge_model)
     P.sor_sweeps, P.newton_max, P.nthreads = int(p.sor_sweeps), int(p.newton_max), int(nthreads)
+    gw = p.G if p.Gw is None else p.Gw  # None: a neutral wall, G_w = G
     for s in range(2):
         for t in range(2):
             P.G[s][t] = float(p.G[s][t]) if s < len(p.G) and t < len(p.G[s]) else 0.0
+            P.Gw[s][t] = float(gw[s][t]) if s < len(gw) and t < len(gw[s]) else 0.0
     info = box.info
-    P.Gw = p.Gw
     P.nu0, P.nu_inf, P.lam = p.nu0, p.nu_inf, p.lam
     P.n_flow = float(info.get("n_flow", p.n_flow))
     P.Q_b = float(info.get("Q_b", p.Q_b))

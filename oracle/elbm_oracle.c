@@ -64,7 +64,7 @@ typedef struct {
     int32_t carreau, curvature, electrostriction, charge_model;
     int32_t sor_sweeps, newton_max, nthreads, pad_;
     double G[2][2];
-    double Gw;
+    double Gw[2][2];
     double nu0, nu_inf, lam, n_flow;
     double Q_b, Q_s, xi_b, xi_s, K_d, rho_th, w_theta;
     double E_ext[3];
@@ -177,13 +177,27 @@ static double phi_fn(double y) {
  * using sum_p Delta_p = 0 (f and f_eq carry the same density).  A
  * non-positive population leaves H(f) undefined: fallback.
  * g is convex on the positivity interval 0 < alpha < alpha_max, g(0) = 0,
- * g'(0) = L, so a root exists iff L < 0 and it is unique.
+ * g'(0) = L.  At the upper end the population that vanishes contributes
+ * f_p phi(-1) = f_p (finite), so g(alpha_max-) is finite: a root exists iff
+ * L < 0 and g(alpha_max-) > 0, and it is then unique.
  * Newton from alpha0 (2 = the BGK limit, or a supplied guess); a step that
- * leaves the positivity interval is halved toward its edge; convergence when
- * |g| <= rtol * sum_p f_p phi(alpha x_p) or the step stalls at rounding.
+ * leaves the positivity interval is halved toward its edge, and the first
+ * time one leaves it at the top, g(alpha_max-) is evaluated: not positive
+ * means no root.  Convergence when |g| <= rtol * sum_p f_p phi(alpha x_p) or
+ * the step stalls at rounding.
  * No root or no convergence: alpha = min(2, 0.99 alpha_max), flagged.
  * Returns the number of Newton updates (>= 0) or -1 on fallback.
  */
+/* g at the top of the positivity interval (see ora_alpha): phi(-1) = 1. */
+static double g_at_alpha_max(const double f[Q], const double x[Q], double L, double amax) {
+    double S = 0.0;
+    for (int p = 0; p < Q; ++p) {
+        double y = amax * x[p];
+        S += f[p] * (y > -1.0 ? phi_fn(y) : 1.0);
+    }
+    return S + amax * L;
+}
+
 double ora_alpha(const double f[Q], const double feq[Q], const double u[3], double rho,
                  double alpha0, double rtol, int maxit, int *iters_out) {
     double D[Q], x[Q];
@@ -209,6 +223,7 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
     double a = alpha0;
     if (!(a > 0.0 && a < amax)) a = 0.5 * (amax < 4.0 ? amax : 4.0);
     if (L < 0.0) {
+        int probed = 0;
         for (int it = 0; it <= maxit; ++it) {
             double S = 0.0, gp = L;
             for (int p = 0; p < Q; ++p) {
@@ -221,7 +236,13 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
             double an;
             if (gp > 0.0) an = a - g / gp;
             else an = 2.0 * a;                      /* left of the minimum of g */
-            if (an >= amax) an = 0.5 * (a + amax);
+            if (an >= amax) {
+                if (!probed) {  /* leaving at the top: is there a root at all? */
+                    probed = 1;
+                    if (!(g_at_alpha_max(f, x, L, amax) > 0.0)) break;
+                }
+                an = 0.5 * (a + amax);
+            }
             if (an <= 0.0) an = 0.5 * a;
             if (fabs(an - a) <= 4.0 * DBL_EPSILON * a) { *iters_out = it + 1; return an; }
             a = an;
@@ -631,7 +652,10 @@ static void electric(ora_state *s) {
 
 /* Shan-Chen interaction (Eq. sc), generalised to components sigma, sigma':
  *   F^s = -psi^s(r) sum_s' G_ss' sum_{p: r+c_p fluid} w_p psi^s'(r+c_p) c_p
- *         - G_w psi^s(r) sum_{p: r+c_p wall} w_p psi^s(r) c_p,
+ *         - psi^s(r) sum_s' Gw_ss' sum_{p: r+c_p wall} w_p psi^s'(r) c_p:
+ * a wall neighbour carries the node's own psi, weighted by the fluid-wall
+ * couplings (one component: the printed form; Gw = G: no net wall force on a
+ * uniform fluid),
  * psi = 1 - exp(-rho) (rho_0 = 1).  The electric force is shared among the
  * components by mass fraction.  Total F^s = F_int^s + F_el^s. */
 static void forces(ora_state *s) {
@@ -662,9 +686,11 @@ static void forces(ora_state *s) {
                         for (int a = 0; a < 3; ++a) acc[a] += WV[p] * sp * CV[p][a];
                     }
                     double ps = s->psi[(int64_t)sg * N + n];
+                    double gw = 0.0;
+                    for (int t = 0; t < C; ++t) gw += s->P.Gw[sg][t] * s->psi[(int64_t)t * N + n];
                     double frac = s->rho[(int64_t)sg * N + n] / rt;
                     for (int a = 0; a < 3; ++a) {
-                        double Fi = -ps * acc[a] - s->P.Gw * ps * ps * wall[a];
+                        double Fi = -ps * acc[a] - ps * gw * wall[a];
                         s->F[((int64_t)sg * 3 + a) * N + n] = Fi + frac * s->Fel[a * N + n];
                     }
                 }

@@ -110,8 +110,10 @@ Model make_model(const elbm_params &P) {
   M.newton_max = P.newton_max;
   M.alpha_guess = P.alpha_guess;
   for (int s = 0; s < 2; ++s)
-    for (int t = 0; t < 2; ++t) M.G[s][t] = P.G[s][t];
-  M.Gw = P.Gw;
+    for (int t = 0; t < 2; ++t) {
+      M.G[s][t] = P.G[s][t];
+      M.Gw[s][t] = P.Gw[s][t];
+    }
   M.nu0 = P.nu0;
   M.nu_inf = P.nu_inf;
   M.lam = P.lam;

@@ -40,7 +40,7 @@ struct BoxDev {
 
 struct Model {
   int32_t C, carreau, curvature, electrostriction, charge_model, newton_max, alpha_guess, pad;
-  double G[2][2], Gw, nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
+  double G[2][2], Gw[2][2], nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
   double rho_in[2], rho_out[2];
 };
 
@@ -384,11 +384,28 @@ __device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
   return a;
 }
 
-// Newton on g from a inside (0, amax) (f, xs as for the set-up pass).
+// g at the top of the positivity interval, g(amax-) = sum_p f_p phi(amax x_p)
+// + amax L, where the population that vanishes contributes f_p phi(-1) = f_p:
+// with L < 0 a root exists in (0, amax) iff this is positive.
+template <typename T>
+__device__ __forceinline__ double alpha_g_top(const T *f, const double *xs, double L, double amax) {
+  double S = 0.0;
+#pragma unroll 1
+  for (int p = 0; p < NQ; ++p) {
+    const double y = amax * xs[p * XSTRIDE];
+    S += double(f[p * BLK]) * (y > -1.0 ? phi_of(y, log1p_fast(y)) : 1.0);
+  }
+  return S + amax * L;
+}
+
+// Newton on g from a inside (0, amax) (f, xs as for the set-up pass).  The
+// first step that would leave the interval at the top checks that a root
+// exists at all (alpha_g_top); none: the fallback at once.
 template <typename T>
 __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double M2,
                                                 double a, double rtol, int maxit, int &iters) {
   {
+    bool probed = false;
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L;
 #pragma unroll 4
@@ -408,7 +425,13 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
       if (it == maxit) break;
       double an = (gp > 0.0) ? a - g / gp : 2.0 * a;
       const bool newton = gp > 0.0 && an > 0.0 && an < amax;
-      if (an >= amax) an = 0.5 * (a + amax);
+      if (an >= amax) {
+        if (!probed) {
+          probed = true;
+          if (!(alpha_g_top<T>(f, xs, L, amax) > 0.0)) break;
+        }
+        an = 0.5 * (a + amax);
+      }
       if (an <= 0.0) an = 0.5 * a;
       if (fabs(an - a) <= 4.0 * 2.220446049250313e-16 * a) {
         iters = it + 1;

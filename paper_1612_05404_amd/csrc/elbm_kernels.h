@@ -300,8 +300,10 @@ __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, dou
 // populations and FP64 moments, (LEARN) run the learned starter over the
 // wave, FP64 alpha, viscosity, collision, store.  Per-lane work is
 // predicated on `fl` so that the matrix-core section runs on whole waves.
+// With FP32 populations two blocks fit a CU's LDS: the register budget is
+// held to two waves per SIMD (matrix accumulators included).
 template <typename T, typename F, int C, bool LEARN>
-__global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W, int record) {
+__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T, F> a, Model M, MlpDev W, int record) {
   // thread-private LDS: populations of the current component (column p * BLK
   // + tid) and, per wave, x_p (column p * 64 + lane), whose 9.5 KB also hold
   // the starter's two [64][32] bf16 tiles before the alpha solve
@@ -429,9 +431,12 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, MlpDev W
       drt += dr;
       const F ps = a.psi[(int64_t)s * a.N + nd.g];
       const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
+      F gw = F(0);  // wall neighbours carry the node's own psi (Eq. sc, wall sum)
+#pragma unroll
+      for (int t = 0; t < C; ++t) gw += F(M.Gw[s][t]) * a.psi[(int64_t)t * a.N + nd.g];
       F Fs[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - F(M.Gw) * ps * ps * wall[d] + frac * Fel[d];
+      for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - ps * gw * wall[d] + frac * Fel[d];
       mom[0] += jx + 0.5 * double(Fs[0]);
       mom[1] += jy + 0.5 * double(Fs[1]);
       mom[2] += jz + 0.5 * double(Fs[2]);

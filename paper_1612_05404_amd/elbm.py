@@ -36,7 +36,7 @@ class elbm_params(ct.Structure):
         ("ncomp", ct.c_int32), ("storage", ct.c_int32), ("carreau", ct.c_int32), ("curvature", ct.c_int32),
         ("electrostriction", ct.c_int32), ("charge_model", ct.c_int32), ("sor_sweeps", ct.c_int32),
         ("newton_max", ct.c_int32), ("alpha_guess", ct.c_int32), ("pad_", ct.c_int32),
-        ("G", (ct.c_double * 2) * 2), ("Gw", ct.c_double),
+        ("G", (ct.c_double * 2) * 2), ("Gw", (ct.c_double * 2) * 2),
         ("nu0", ct.c_double), ("nu_inf", ct.c_double), ("lam", ct.c_double), ("K_d", ct.c_double),
         ("rho_th", ct.c_double), ("w_theta", ct.c_double), ("xi_b", ct.c_double), ("xi_s", ct.c_double),
         ("newton_rtol", ct.c_double), ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
@@ -136,10 +136,12 @@ def make_params(p, storage: int, guess: int = 0) -> elbm_params:
     P.carreau, P.curvature, P.electrostriction = int(p.carreau), int(p.curvature), int(p.electrostriction)
     P.charge_model, P.sor_sweeps, P.newton_max = int(p.charge_model), int(p.sor_sweeps), int(p.newton_max)
     P.alpha_guess = int(guess)
+    gw = p.G if p.Gw is None else p.Gw
     for s in range(2):
         for t in range(2):
             P.G[s][t] = float(p.G[s][t]) if s < len(p.G) and t < len(p.G[s]) else 0.0
-    P.Gw, P.nu0, P.nu_inf, P.lam, P.K_d = p.Gw, p.nu0, p.nu_inf, p.lam, p.K_d
+            P.Gw[s][t] = float(gw[s][t]) if s < len(gw) and t < len(gw[s]) else 0.0
+    P.nu0, P.nu_inf, P.lam, P.K_d = p.nu0, p.nu_inf, p.lam, p.K_d
     P.rho_th, P.w_theta, P.xi_b, P.xi_s, P.newton_rtol = p.rho_th, p.w_theta, p.xi_b, p.xi_s, p.newton_rtol
     for s in range(2):
         P.rho_in[s], P.rho_out[s] = p.rho_in[s], p.rho_out[s]

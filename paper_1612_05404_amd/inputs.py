@@ -54,9 +54,10 @@ def uniform(seed: int, n: int, lo: float, hi: float, offset: int = 0) -> np.ndar
 @dataclass
 class Params:
     ncomp: int = 2
-    # Shan-Chen couplings G[s][t] and the wall coupling
+    # Shan-Chen couplings G[s][t] and the fluid-wall couplings Gw[s][t]
+    # (None: Gw = G, a neutral wall)
     G: List[List[float]] = field(default_factory=lambda: [[0.0, 3.0], [3.0, 0.0]])
-    Gw: float = 0.0
+    Gw: Optional[List[List[float]]] = None
     # rheology: Newtonian nu0 unless carreau
     carreau: int = 0
     nu0: float = 1.0 / 6.0

@@ -241,6 +241,36 @@ def test_shan_chen_pair_sum_vanishes(ora):
     assert np.abs(F).max() > 1e-2
 
 
+@pytest.mark.parametrize("gw", ["neutral", "zero", "random"])
+def test_shan_chen_wall_term_closed_form(ora, gw):
+    # Eq. sc, wall sum: a wall neighbour carries the node's own psi.  On a
+    # uniform fluid between two walls the fluid sum is psi times the weights
+    # of the fluid neighbours, so only the layers next to a wall feel a force:
+    # with W = sum_{wall} w_p c_p = (0, 0, -+1/6) (one axis and four diagonal
+    # neighbours), F^s = -psi^s sum_t (Gw_st - G_st) psi^t W.  Gw = G (the
+    # default) leaves no force at all.
+    G = np.array([[0.0, 8.26], [8.26, 0.0]])
+    Gw = {"neutral": None, "zero": np.zeros((2, 2)),
+          "random": np.random.default_rng(7).uniform(-6.0, 6.0, (2, 2))}[gw]
+    nz = 8
+    b = _box(6, 5, nz, 0.3, walls_z=True)
+    p = inputs.base_params(Q_b=0.0, Q_s=0.0, sor_sweeps=0, G=G.tolist(),
+                           Gw=None if Gw is None else Gw.tolist())
+    o = ora.Oracle(p, b, nthreads=2)
+    o.step(1)
+    F = o.field(ora.F_F)  # [C][3][nz][ny][nx]
+    psi = 1.0 - np.exp(-np.array([0.3, 0.71]))
+    D = (G if Gw is None else Gw) - G
+    want = np.zeros_like(F)
+    for s in range(2):
+        f_s = -psi[s] * float(D[s] @ psi)
+        want[s, 2, 1] = f_s * (-1.0 / 6.0)
+        want[s, 2, nz - 2] = f_s * (1.0 / 6.0)
+    assert np.abs(F - want).max() < 1e-14
+    if gw == "zero":  # the missing repulsive neighbours push each component towards the wall
+        assert F[0, 2, 1].max() < -1e-3 and F[0, 2, nz - 2].min() > 1e-3
+
+
 def _sc_coexistence_theory(G):
     """Liquid/vapour densities of the single-component Shan-Chen fluid with
     psi = 1 - exp(-rho) from the mechanical-stability condition

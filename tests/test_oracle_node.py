@@ -184,6 +184,61 @@ def test_alpha_no_root_falls_back(ora):
     assert it == -1 and a == min(2.0, 0.99 * amax)
 
 
+def _minority_node(ora, seed):
+    """A dilute, fast, strongly distorted node, as the minority component of
+    a two-component interface: rho ~ 0.01-0.05, |u| up to 0.25."""
+    c, w = ora.lattice()
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.01, 0.05)
+    u0 = rng.normal(size=3)
+    u0 *= rng.uniform(0.05, 0.25) / np.linalg.norm(u0)
+    f = rho * ora.feq(1.0, u0) * (1 + rng.uniform(-0.5, 1.5, 19))
+    r = f.sum()
+    u = (c.T @ f) / r
+    fe = ora.feq(r, u)
+    x = (fe - f) / f
+    return f, fe, u, r, w, np.min(-1 / x[x < 0])
+
+
+def _g_dec(f, fe, w, a):
+    """H(f + a (fe - f)) - H(f) in 60-digit decimal; a vanishing population
+    contributes 0 ln 0 = 0 (the limit at the top of the positivity interval)."""
+    getcontext().prec = 60
+    F = [Decimal(float(v)) for v in f]
+    E = [Decimal(float(v)) for v in fe]
+    W = [Decimal(1) / Decimal(3)] + [Decimal(1) / Decimal(18)] * 6 + [Decimal(1) / Decimal(36)] * 12
+    A = Decimal(float(a))
+    P = [fi + A * (ei - fi) for fi, ei in zip(F, E)]
+    return float(sum(pi * (pi / wi).ln() for pi, wi in zip(P, W) if pi > 0) - _H_dec(F, W))
+
+
+@pytest.mark.parametrize("seed", [16, 20, 29])
+def test_alpha_no_root_in_positivity_interval(ora, seed):
+    # L < 0, yet H(f + alpha Delta) stays below H(f) up to the top of the
+    # positivity interval, where one population vanishes: no entropy-preserving
+    # mirror state exists, and the fallback min(2, 0.99 alpha_max) is returned.
+    f, fe, u, r, w, amax = _minority_node(ora, seed)
+    assert np.sum((fe - f) * np.log(f / (w * r))) < 0
+    xs = np.concatenate([np.linspace(1e-3, amax * (1 - 1e-9), 60), [amax]])
+    assert max(_g_dec(f, fe, w, t) for t in xs) < 0
+    a, it = ora.alpha(f, fe, u, r)
+    assert it == -1 and a == min(2.0, 0.99 * amax)
+
+
+@pytest.mark.parametrize("seed", [5, 12])
+def test_alpha_root_near_top_of_positivity_interval(ora, seed):
+    # The root lies within a few per cent of alpha_max, where Newton steps from
+    # 2 leave the interval: it must still be found, and be the literal one.
+    f, fe, u, r, w, amax = _minority_node(ora, seed)
+    a, it = ora.alpha(f, fe, u, r)
+    assert it >= 0 and a > 0.97 * amax
+    grid = np.linspace(0.5 * amax, amax * (1 - 1e-12), 200)
+    g = [_g_dec(f, fe, w, t) for t in grid]
+    k = next(i for i in range(len(g) - 1) if g[i] < 0 <= g[i + 1])
+    ref = _alpha_decimal(f, fe, w, grid[k], grid[k + 1])
+    assert abs(a - ref) <= 1e-11 * ref, (a, ref)
+
+
 @pytest.mark.parametrize("seed", range(10))
 def test_sym3_norm_vs_eigvalsh(ora, seed):
     rng = np.random.default_rng(seed)
