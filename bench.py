@@ -40,8 +40,8 @@ ROOF_AT, ROOF_STEPS = 250, 16  # the collision's roofline window: steps 251..266
 # node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
 # instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
 # factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 16120
-COLLIDE_TRAFFIC_BYTES = 1_042_623_066
+COLLIDE_FP64_FLOP_PER_NODE = 15334
+COLLIDE_TRAFFIC_BYTES = 587_447_794
 
 
 def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -61,7 +61,7 @@ def step_bytes_per_node(storage_bytes: int, ncomp: int, sor_sweeps: int) -> int:
     return 2 * ncomp * 19 * storage_bytes + 10 * storage_bytes + 4 * storage_bytes * sor_sweeps
 
 
-def cpu_baseline(wl, budget_s: float = 12.0, max_steps: int = 20):
+def cpu_baseline(wl, budget_s: float = 15.0, max_steps: int = 200):
     import oracle
     oracle.build(force=False)
     box = wl.boxes[0]
