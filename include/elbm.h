@@ -90,7 +90,8 @@ typedef struct {
     double rho_th, w_theta;   /* smoothed Heaviside: 0.5(1+tanh((rho-rho_th)/w))    */
     double xi_b, xi_s;        /* generator-connected charge constants (Eq. surface-q3) */
     double newton_rtol;       /* alpha converged when |dH| <= rtol * scale          */
-    double rho_in[2];         /* component densities held at inlet nodes            */
+    double rho_in[2];         /* inlet densities at start, and for an inlet node
+                                 without fluid neighbours                           */
     double rho_out[2];        /* component densities held at outlet nodes           */
 } elbm_params;
 
@@ -137,7 +138,11 @@ elbm_status elbm_bind(elbm_ctx *ctx, void *dev_arena, size_t bytes, void *hip_st
  *  u_bc [3][N] inlet velocity (read at inlet nodes only; may be NULL);
  *  xi [C][19][N] jitter draws (may be NULL = no jitter); jitter amplitude.
  * Fluid nodes start at f = f_eq(rho, u) (1 + jitter * xi), inlet nodes at
- * f_eq(rho_in, u_bc), outlet nodes at f_eq(rho_out, 0), solid nodes at 0. */
+ * f_eq(rho_in, u_bc), outlet nodes at f_eq(rho_out, 0), solid nodes at 0.
+ * Every step resets an inlet node to f_eq(rho_nb, u_bc) per component, rho_nb
+ * the w-weighted mean density of its fluid neighbours (a velocity inlet whose
+ * density is that of the liquid next to it, as in the jet set-up of Sec. IV);
+ * outlet nodes keep theirs. */
 elbm_status elbm_set_box(elbm_ctx *ctx, int32_t box, const uint8_t *node_type, const double *rho,
                          const double *u, const double *phi, const double *u_bc, const double *xi,
                          double jitter);

@@ -377,8 +377,9 @@ void ora_destroy(ora_state *s) {
     free(s);
 }
 
-/* Boundary-node populations: inlet nodes hold f_eq(rho_in, u_bc), outlet
- * nodes f_eq(rho_out, 0); neither streams nor collides. */
+/* Initial boundary-node populations: inlet nodes f_eq(rho_in, u_bc), outlet
+ * nodes f_eq(rho_out, 0).  Neither streams nor collides; outlet nodes keep
+ * theirs, inlet nodes are reset every step (see inlet_populations). */
 static void boundary_populations(ora_state *s, int64_t n, int sigma, double out[Q]) {
     double u[3] = {0, 0, 0};
     double r;
@@ -697,6 +698,25 @@ static void forces(ora_state *s) {
             }
 }
 
+/* Velocity inlet (the jet set-up of Sec. IV: Poiseuille velocity at the
+ * inlet nodes, density that of the liquid): after each step's moments an
+ * inlet node holds f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted
+ * mean density of its fluid neighbours, sum_p w_p rho(r + c_p) / sum_p w_p
+ * (rho_in when it has none). */
+static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, double out[Q]) {
+    const int64_t N = s->N;
+    const int64_t n = node_index(s, x, y, z);
+    double sw = 0.0, sr = 0.0;
+    for (int p = 1; p < Q; ++p) {
+        int64_t m = neighbour(s, x, y, z, CV[p][0], CV[p][1], CV[p][2]);
+        if (m < 0 || kind(s, m) != T_FLUID) continue;
+        sw += WV[p];
+        sr += WV[p] * s->rho[(int64_t)sg * N + m];
+    }
+    double u[3] = {s->u_bc[n], s->u_bc[N + n], s->u_bc[2 * N + n]};
+    ora_feq(sw > 0.0 ? sr / sw : s->P.rho_in[sg], u, out);
+}
+
 /* Collision (Eq. lattice-b) with alpha (Eq. entropic), beta from the
  * Newtonian or Carreau viscosity (Eqs. strain, stress, strain2, carreau,
  * beta) and the exact-difference source S = f_eq(rho, u + F/rho) - f_eq(rho, u)
@@ -724,9 +744,15 @@ static void collide(ora_state *s) {
                 for (int sg = 0; sg < C; ++sg) {
                     double *fo = s->fn + (int64_t)sg * Q * N;
                     if (k != T_FLUID) {
-                        /* boundary nodes keep their populations */
+                        /* outlet and solid nodes keep their populations; inlet nodes are reset */
                         const double *fs = s->f + (int64_t)sg * Q * N;
-                        for (int p = 0; p < Q; ++p) fo[p * N + n] = fs[p * N + n];
+                        if (k == T_INLET) {
+                            double fi[Q];
+                            inlet_populations(s, x, y, z, sg, fi);
+                            for (int p = 0; p < Q; ++p) fo[p * N + n] = fi[p];
+                        } else {
+                            for (int p = 0; p < Q; ++p) fo[p * N + n] = fs[p * N + n];
+                        }
                         s->alpha[(int64_t)sg * N + n] = 0.0;
                         s->iters[(int64_t)sg * N + n] = 0;
                         s->nu[(int64_t)sg * N + n] = 0.0;

@@ -56,6 +56,7 @@ struct Ptrs {
   T *fa, *fb;           // populations: read fa, write fb
   F *rho, *psi, *grad, *bulk, *surf, *q, *phi, *rhs, *e2;  // grad: unit normal [3], |grad rho_A|^2
   F *rec_u;
+  const F *ubc;         // [3][N] inlet velocity (read at inlet nodes)
   double *rec_alpha;
   int32_t *rec_iters;
   uint8_t *type;

@@ -295,6 +295,34 @@ __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, dou
   }
 }
 
+// Velocity inlet (the jet set-up of Sec. IV: Poiseuille velocity at the inlet
+// nodes, density that of the liquid): each step an inlet node is reset to
+// f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted mean density of its
+// fluid neighbours (rho_in when it has none).  Written to the output buffer,
+// which the next step pulls from.
+template <typename T, typename F, int C>
+__device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M, const Node &nd) {
+  double sw = 0.0, sr[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) sr[s] = 0.0;
+#pragma unroll 1
+  for (int p = 1; p < NQ; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+    if (m < 0 || (a.type[nd.B.off + m] & 3) != K_FLUID) continue;
+    sw += wgt(p);
+#pragma unroll
+    for (int s = 0; s < C; ++s) sr[s] += wgt(p) * double(a.rho[(int64_t)s * a.N + nd.B.off + m]);
+  }
+  const double ux = double(a.ubc[nd.g]), uy = double(a.ubc[a.N + nd.g]), uz = double(a.ubc[2 * a.N + nd.g]);
+  const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const double r = sw > 0.0 ? sr[s] / sw : M.rho_in[s];
+#pragma unroll 1
+    for (int p = 0; p < NQ; ++p) a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = T(feq<double>(p, r, ux, uy, uz, uu));
+  }
+}
+
 // The collision (Eq. lattice-b) at fluid nodes with every force term.
 // Forces come first (fields only); then each component in turn: pull its 19
 // populations and FP64 moments, (LEARN) run the learned starter over the
@@ -521,6 +549,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
       a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
     }
   }
+  if (nd.live && k == K_INLET) inlet_store<T, F, C>(a, M, nd);
   // ---- counters: wave sums, one atomic per wave and counter
   c_fb = wave_sum_u64(c_fb);
   c_it = wave_sum_u64(c_it);

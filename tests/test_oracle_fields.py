@@ -67,6 +67,30 @@ def test_bounce_back_at_walls(ora):
     assert np.allclose(m1, m0, rtol=1e-13, atol=0)
 
 
+def test_velocity_inlet_at_rest_keeps_the_fluid(ora):
+    # The jet set-up of Sec. IV prescribes the inlet velocity; the inlet density
+    # follows the liquid next to it.  With u_bc = 0 an inlet plane under a
+    # fluid at density 0.5 must then act as a closed, non-slip end: after the
+    # first step's exchange with the initial inlet state (rho_in = 1.0) the
+    # fluid relaxes to rest at its own density, uniform, and is not driven to
+    # rho_in as a fixed-density reservoir would drive it.
+    nz = 16
+    b = inputs.droplet_box(4, 4, nz, 1.0, seed=3, walls_z=True, ncomp=1, jitter=0.0)
+    b.node_type[0] = inputs.INLET
+    r0 = 0.5 * np.ones((nz, 4, 4))
+    r0[0] = r0[nz - 1] = 0.0
+    b.rho0 = r0[None].copy()
+    p = inputs.base_params(ncomp=1, G=[[0.0]], Q_b=0.0, Q_s=0.0, sor_sweeps=0, rho_in=[1.0, 0.0])
+    o = ora.Oracle(p, b, nthreads=2)
+    o.step(3000)
+    r = o.field(ora.F_RHO)[0][1:nz - 1]
+    u = o.field(ora.F_UPH)[:, 1:nz - 1]
+    assert np.abs(u).max() < 1e-10
+    assert r.max() - r.min() < 1e-10
+    # one step of (rho_in - 0.5)/6 per inlet-adjacent node, then a bounded transient
+    assert 0.5 < r.mean() < 0.5 + 0.5 / 6 * 2 / (nz - 2)
+
+
 def test_collision_node_invariants(ora):
     # Per node and component: the collision keeps the mass and adds exactly the
     # force to the momentum (Eq. lattice-b with the exact-difference source Eq. add).
