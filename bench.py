@@ -12,11 +12,12 @@ Prints one JSON line: MLUPS (million lattice-node updates per second) over K
 steps (default 2000, the whole configured run, after W warm-up steps from the
 initial state) replayed as captured step graphs, in the launch mapping the
 autotuner chose on a separate instance; the per-phase breakdown of the same
-W + K steps from HIP events on the library's stream (second instance); the
-roofline of the dominant kernel (the collision, bound by FP64 arithmetic; its
-HBM roofline beside it) from its event-timed launches over steps 251..266,
-the window its hardware counters are taken on (third instance); and the CPU
-oracle timed on a bounded sample.
+W + K steps from HIP events on the library's stream (second instance, phases
+in order on one stream); the rooflines of the two collision kernels from their
+event-timed launches over steps 251..266, the window their hardware counters
+are taken on (third instance): k_alpha, the dominant one, bound by FP64
+arithmetic (its HBM roofline beside it), and k_collide against HBM; and the
+CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -32,26 +33,35 @@ METRIC = "MLUPS coupled step, % of HBM roofline; learned-α vs plain Newton, sam
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 COPY_MIB = 256
-ROOF_AT, ROOF_STEPS = 250, 16  # the collision's roofline window: steps 251..266
+ROOF_AT, ROOF_STEPS = 250, 16  # the roofline window: steps 251..266
 
 # Counted with rocprofv3 --pmc on the default workload with the series
-# starter and the autotuner's mapping, over the collision launches of steps
-# 251..266 (early steps need more Newton updates): FP64 operations per
-# node of one launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave
-# instructions), and its HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
-# factors a plain 256 MiB copy gives for the same counters).
-COLLIDE_FP64_FLOP_PER_NODE = 15334
-COLLIDE_TRAFFIC_BYTES = 587_447_794
+# starter and the autotuner's mapping, over the launches of steps 251..266
+# (early steps need more Newton updates): FP64 operations per node of one
+# k_alpha launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave instructions),
+# and the HBM bytes of one launch of each kernel (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives for the same
+# counters).  None: not counted for the current kernels.
+ALPHA_FP64_FLOP_PER_NODE = 13199
+ALPHA_TRAFFIC_BYTES = 369_239_038
+COLLIDE_TRAFFIC_BYTES = 220_014_025
 
 
-def collide_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
-    """Algorithmic HBM bytes of one collision per node: the 19 pulled
-    populations of each component read once and written once, plus the
-    neighbour fields read once (psi per component, phi, |E|^2) and the node's
-    own charge, liquid density and type byte."""
+def alpha_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
+    """Algorithmic HBM bytes of k_alpha per node: the 19 pulled populations of
+    each component read once, alpha * beta (FP64) written per component, and
+    the node's type byte."""
+    return ncomp * 19 * storage_bytes + ncomp * 8 + 1
+
+
+def collide_bytes_per_node(storage_bytes: int, field_bytes: int, ncomp: int) -> int:
+    """Algorithmic HBM bytes of k_collide per node: the 19 pulled populations
+    of each component read once and written once, alpha * beta read, the
+    neighbour fields read once (psi per component, phi, |E|^2), the node's
+    charge and component densities, and its type byte."""
     pops = 2 * ncomp * 19 * storage_bytes
-    fields = (ncomp + 4) * storage_bytes + 1
-    return pops + fields
+    fields = (ncomp + 2 + 1 + ncomp) * field_bytes
+    return pops + ncomp * 8 + fields + 1
 
 
 def step_bytes_per_node(storage_bytes: int, ncomp: int, sor_sweeps: int) -> int:
@@ -231,20 +241,21 @@ def main():
         return launch
 
     def roofline_window(mode, launch):
-        # collision time over the window where the counters are taken
+        # k_alpha and k_collide times over the window where the counters are taken
         lat = make(mode, launch)
         lat.step(ROOF_AT, record=False)
         lat.set_timing(True)
         lat.step(ROOF_STEPS, record=False)
         ph = lat.timing()
         lat.close()
-        return ph["collide"] / max(ph["steps"], 1)
+        n = max(ph["steps"], 1)
+        return ph["alpha"] / n, ph["collide"] / n
 
     if args.roofline_only:
         launch = tuned_launch(args.alpha_guess)
-        ms = roofline_window(args.alpha_guess, launch)
-        print(json.dumps({"roofline_window": {"steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS], "collide_ms": round(ms, 5),
-                                              "launch": launch}}), flush=True)
+        ams, cms = roofline_window(args.alpha_guess, launch)
+        print(json.dumps({"roofline_window": {"steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS], "alpha_ms": round(ams, 5),
+                                              "collide_ms": round(cms, 5), "launch": launch}}), flush=True)
         return
 
     results = {}
@@ -286,11 +297,15 @@ def main():
     dt, ph, diag = r["dt"], r["ph"], r["diag"]
     mlups = nodes * args.steps / dt / 1e6
     steps_timed = max(ph["steps"], 1)
-    coll_ms = r["roof_ms"]
-    cb = collide_bytes_per_node(esz, wl.params.ncomp)
-    achieved = cb * nodes / (coll_ms * 1e-3) / 1e9
+    al_ms, co_ms = r["roof_ms"]
+    fesz = 4 if wl.dtype == "f32all" else 8
+    ab_ = alpha_bytes_per_node(esz, wl.params.ncomp)
+    cb = collide_bytes_per_node(esz, fesz, wl.params.ncomp)
+    al_gbs = ab_ * nodes / (al_ms * 1e-3) / 1e9
+    co_gbs = cb * nodes / (co_ms * 1e-3) / 1e9
     counted = wl.name == "efield_drop" and args.alpha_guess == "series"
-    tflops = COLLIDE_FP64_FLOP_PER_NODE * nodes / (coll_ms * 1e-3) / 1e12 if counted else None
+    flop = ALPHA_FP64_FLOP_PER_NODE if counted else None
+    tflops = flop * nodes / (al_ms * 1e-3) / 1e12 if flop else None
     sb = step_bytes_per_node(esz, wl.params.ncomp, wl.params.sor_sweeps)
     comparison = {
         m: {"mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
@@ -322,27 +337,38 @@ def main():
             "launch": r["launch"],
         },
         "roofline": {
-            "kernel": "k_collide",
+            "kernel": "k_alpha",
             "bound": "alu",
-            "achieved": round(tflops, 3) if counted else None,
+            "achieved": round(tflops, 3) if tflops else None,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(tflops / FP64_PEAK_TFLOPS, 4) if counted else None,
-            "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
-            "fp64_flop_per_node": COLLIDE_FP64_FLOP_PER_NODE if counted else None,
-            "avg_ms": round(coll_ms, 5),
+            "frac": round(tflops / FP64_PEAK_TFLOPS, 4) if tflops else None,
+            "traffic": ALPHA_TRAFFIC_BYTES if counted else None,
+            "fp64_flop_per_node": flop,
+            "avg_ms": round(al_ms, 5),
             "window_steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS],
         },
         "roofline_hbm": {
-            "kernel": "k_collide",
+            "kernel": "k_alpha",
             "bound": "hbm",
-            "achieved": round(achieved, 2),
+            "achieved": round(al_gbs, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(al_gbs / HBM_PEAK_GBS, 4),
+            "traffic": ALPHA_TRAFFIC_BYTES if counted else None,
+            "bytes_per_node": ab_,
+            "avg_ms": round(al_ms, 5),
+        },
+        "roofline_collide": {
+            "kernel": "k_collide",
+            "bound": "hbm",
+            "achieved": round(co_gbs, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(co_gbs / HBM_PEAK_GBS, 4),
             "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
             "bytes_per_node": cb,
-            "avg_ms": round(coll_ms, 5),
+            "avg_ms": round(co_ms, 5),
         },
         "step_effective_gbs": round(sb * mlups * 1e6 / 1e9, 2),
         "step_bytes_per_node": sb,

@@ -189,14 +189,17 @@ enum {
     ELBM_PHASE_CHARGE = 1,    /* gradient, curvature, charge reductions, Poisson rhs */
     ELBM_PHASE_POISSON = 2,   /* red-black SOR sweeps (+ zero-mean gauge)          */
     ELBM_PHASE_EFIELD = 3,    /* |E|^2                                             */
-    ELBM_PHASE_COLLIDE = 4,   /* forces, alpha, rheology, collision                */
-    ELBM_NPHASES = 5
+    ELBM_PHASE_ALPHA = 4,     /* pull, entropic alpha, rheology (k_alpha)          */
+    ELBM_PHASE_COLLIDE = 5,   /* forces, collision update, inlet nodes (k_collide) */
+    ELBM_NPHASES = 6
 };
 
 /* Device timing of every phase: enable != 0 records HIP events on the bound
  * stream around each phase of each following step (a small overhead between
  * launches); enable == 0 stops and discards.  Host-side events only, no device
- * memory. */
+ * memory.  Without timing the alpha phase runs on a second stream of the
+ * library, beside the density .. E-field phases; with timing every phase
+ * runs in order on the bound stream. */
 elbm_status elbm_set_timing(elbm_ctx *ctx, int32_t enable);
 
 /* Waits for the stream and returns the accumulated device milliseconds per

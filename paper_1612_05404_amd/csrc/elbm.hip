@@ -42,13 +42,16 @@ struct elbm_ctx {
   int nblocks = 0;
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
-  size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_reca,
+  size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_reca,
       o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_scal, o_cnt, o_err, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
   char *base = nullptr;
   hipStream_t stream = nullptr;
+  // second stream for the alpha solve beside the field chain, and its fork/join events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool bound = false;
   bool any_gauge = false;
   int parity = 0;  // which population buffer is current (0: fa region)
@@ -57,7 +60,7 @@ struct elbm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  double phase_ms[ELBM_NPHASES] = {0, 0, 0, 0, 0};
+  double phase_ms[ELBM_NPHASES] = {0, 0, 0, 0, 0, 0};
   int64_t timed_steps = 0;
   // launch mapping: XCD-aware block order, steps per captured graph (even),
   // block tile shape of the collision (0: linear)
@@ -82,6 +85,9 @@ struct elbm_ctx {
   ~elbm_ctx() {
     drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -147,6 +153,7 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.e2 = (F *)(b + c->o_e2);
   a.rec_u = (F *)(b + c->o_recu);
   a.ubc = (const F *)(b + c->o_ubc);
+  a.ab = (double *)(b + c->o_ab);
   a.rec_alpha = (double *)(b + c->o_reca);
   a.rec_iters = (int32_t *)(b + c->o_reci);
   a.type = (uint8_t *)(b + c->o_type);
@@ -227,6 +234,21 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     ev = c->ev_pool.data() + c->ev_used;
     c->ev_used += per;
   }
+  // k_alpha needs only the populations: without phase timing it runs on the
+  // second stream beside the field chain (density .. E), and k_collide waits
+  // for it; with timing everything runs in order on the bound stream.
+  const dim3 cgrid(c->tile ? (unsigned)c->ntiles[c->tile] : grid.x);
+  const bool fork = !c->timing;
+  hipStream_t as = fork ? c->aux : c->stream;
+  if (fork) {
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    if (M.alpha_guess == ELBM_GUESS_MLP)
+      hipLaunchKernelGGL((k_alpha<T, F, C, true>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+    else
+      hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+    HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+  }
   mark(c, ev, 0);
   hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
   mark(c, ev, 1);
@@ -247,12 +269,17 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   mark(c, ev, 3);
   hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 4);
-  const dim3 cgrid(c->tile ? (unsigned)c->ntiles[c->tile] : grid.x);
-  if (M.alpha_guess == ELBM_GUESS_MLP)
-    hipLaunchKernelGGL((k_collide<T, F, C, true>), cgrid, blk, 0, c->stream, a, M, make_mlp(c), rec);
-  else
-    hipLaunchKernelGGL((k_collide<T, F, C, false>), cgrid, blk, 0, c->stream, a, M, make_mlp(c), rec);
+  if (fork) {
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  } else {
+    if (M.alpha_guess == ELBM_GUESS_MLP)
+      hipLaunchKernelGGL((k_alpha<T, F, C, true>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+    else
+      hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+  }
   mark(c, ev, 5);
+  hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
+  mark(c, ev, 6);
   c->parity ^= 1;
   HIPCHK(c, hipGetLastError());
   return ELBM_OK;
@@ -501,6 +528,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_e2 = take((size_t)N * e);
   c->o_recu = take(3 * (size_t)N * e);
   c->o_ubc = take(3 * (size_t)N * e);
+  c->o_ab = take((size_t)C * N * 8);
   c->o_reca = take((size_t)C * N * 8);
   c->o_reci = take((size_t)C * N * 4);
   c->o_type = take((size_t)N);
@@ -542,6 +570,11 @@ elbm_status elbm_bind(elbm_ctx *c, void *arena, size_t bytes, void *stream) {
   c->drop_graphs();
   c->base = (char *)arena;
   c->stream = (hipStream_t)stream;
+  if (!c->aux) {  // default priority, like the caller's stream
+    HIPCHK(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
   c->parity = 0;
   c->any_gauge = false;
   // Dirichlet flags come with the node types; assume none until set_box

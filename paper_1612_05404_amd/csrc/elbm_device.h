@@ -57,6 +57,7 @@ struct Ptrs {
   F *rho, *psi, *grad, *bulk, *surf, *q, *phi, *rhs, *e2;  // grad: unit normal [3], |grad rho_A|^2
   F *rec_u;
   const F *ubc;         // [3][N] inlet velocity (read at inlet nodes)
+  double *ab;           // [C][N] alpha * beta of the step's collision
   double *rec_alpha;
   int32_t *rec_iters;
   uint8_t *type;

@@ -323,15 +323,21 @@ __device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M,
   }
 }
 
-// The collision (Eq. lattice-b) at fluid nodes with every force term.
-// Forces come first (fields only); then each component in turn: pull its 19
-// populations and FP64 moments, (LEARN) run the learned starter over the
-// wave, FP64 alpha, viscosity, collision, store.  Per-lane work is
-// predicated on `fl` so that the matrix-core section runs on whole waves.
-// With FP32 populations two blocks fit a CU's LDS: the register budget is
-// held to two waves per SIMD (matrix accumulators included).
+// The collision (Eq. lattice-b) in two kernels.  The entropic alpha (Eq.
+// entropic) and the Carreau viscosity depend only on the pulled populations,
+// not on the forces, so k_alpha needs nothing of the step's field chain
+// (densities, charge, Poisson, E) and runs beside it on a second stream; it
+// leaves alpha * beta per node and component.  k_collide then adds the forces
+// and writes the post-collision populations.
+
+// k_alpha: for each fluid node and component, pull the 19 populations and
+// their FP64 moments, (LEARN) run the learned starter over the wave, solve
+// alpha in FP64, evaluate the viscosity, store ab = alpha c_s^2/(2 nu + c_s^2).
+// Per-lane work is predicated on `fl` so that the matrix-core section runs on
+// whole waves.  With FP32 populations two blocks fit a CU's LDS: the register
+// budget is held to two waves per SIMD (matrix accumulators included).
 template <typename T, typename F, int C, bool LEARN>
-__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T, F> a, Model M, MlpDev W, int record) {
+__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F> a, Model M, MlpDev W, int record) {
   // thread-private LDS: populations of the current component (column p * BLK
   // + tid) and, per wave, x_p (column p * 64 + lane), whose 9.5 KB also hold
   // the starter's two [64][32] bf16 tiles before the alpha solve
@@ -343,14 +349,11 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
   if (a.tx) decode_tile(a, nd);
   else decode(a, nd);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned long long c_fb = 0, c_it = 0, c_neg = 0, c_nf = 0, c_col = 0;
+  unsigned long long c_fb = 0, c_it = 0, c_col = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
   const bool fl = nd.live && k == K_FLUID;
   int nl[NQ];
   unsigned solid = 0u;
-  F acc[C][3], wall[3] = {F(0), F(0), F(0)}, Fel[3] = {F(0), F(0), F(0)}, rt = F(1);
-#pragma unroll
-  for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
   if (fl) {
     // ---- neighbours: local index, solid-or-outside flag
     nl[0] = nd.n;
@@ -359,53 +362,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
       nl[p] = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
       if (nl[p] < 0 || (a.type[nd.B.off + nl[p]] & 3) == K_SOLID) solid |= 1u << p;
     }
-    // ---- Shan-Chen (Eq. sc) and electric (Eq. force_el2) forces
-    F gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
-    const F phic = a.phi[nd.g], e2c = a.e2[nd.g];
-#pragma unroll
-    for (int p = 1; p < NQ; ++p) {
-      const int m = nl[p];
-      const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
-      if ((solid >> p) & 1u) {
-        wall[0] += F(wgt(p) * kCx[p]);
-        wall[1] += F(wgt(p) * kCy[p]);
-        wall[2] += F(wgt(p) * kCz[p]);
-      } else {
-        F ps[C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) ps[t] = a.psi[(int64_t)t * a.N + gm];
-#pragma unroll
-        for (int s = 0; s < C; ++s) {
-          F sp = F(0);
-#pragma unroll
-          for (int t = 0; t < C; ++t) sp += F(M.G[s][t]) * ps[t];
-          acc[s][0] += F(wgt(p)) * sp * F(kCx[p]);
-          acc[s][1] += F(wgt(p)) * sp * F(kCy[p]);
-          acc[s][2] += F(wgt(p)) * sp * F(kCz[p]);
-        }
-      }
-      const F vp = m >= 0 ? a.phi[gm] : phic;
-      const F ve = m >= 0 ? a.e2[gm] : e2c;
-      gp[0] += F(wgt(p) * kCx[p]) * vp;
-      gp[1] += F(wgt(p) * kCy[p]) * vp;
-      gp[2] += F(wgt(p) * kCz[p]) * vp;
-      ge[0] += F(wgt(p) * kCx[p]) * ve;
-      ge[1] += F(wgt(p) * kCy[p]) * ve;
-      ge[2] += F(wgt(p) * kCz[p]) * ve;
-    }
-    const F qn = a.q[nd.g];
-    const F rA = a.rho[nd.g];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const F E = F(nd.B.E[d]) - gp[d] / F(CS2);
-      Fel[d] = qn * E;
-      if (M.electrostriction) Fel[d] += F(0.5) * rA * (ge[d] / F(CS2));
-    }
-    rt = F(0);
-#pragma unroll
-    for (int s = 0; s < C; ++s) rt += a.rho[(int64_t)s * a.N + nd.g];
   }
-  double mom[3] = {0.0, 0.0, 0.0}, drt = 0.0;
   T *f = lds_f + threadIdx.x;
   double *xs = lds_x + wv * (NQ * 64) + lane;
 #pragma unroll
@@ -456,18 +413,6 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
       }
     }
     if (fl) {
-      drt += dr;
-      const F ps = a.psi[(int64_t)s * a.N + nd.g];
-      const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
-      F gw = F(0);  // wall neighbours carry the node's own psi (Eq. sc, wall sum)
-#pragma unroll
-      for (int t = 0; t < C; ++t) gw += F(M.Gw[s][t]) * a.psi[(int64_t)t * a.N + nd.g];
-      F Fs[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - ps * gw * wall[d] + frac * Fel[d];
-      mom[0] += jx + 0.5 * double(Fs[0]);
-      mom[1] += jy + 0.5 * double(Fs[1]);
-      mom[2] += jz + 0.5 * double(Fs[2]);
       // ---- alpha: Newton polish from the starter
       const double uu = ux * ux + uy * uy + uz * uz;
       int its;
@@ -496,29 +441,146 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
         const R lg = R(M.lam) * gd;
         nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow(R(1) + lg * lg, R(0.5) * (nf - R(1))));
       }
-      const double ab = al * (CS2 / (2.0 * nu + CS2));
-      // ---- exact-difference source (Eq. add): with v = u + F/rho,
-      // f_eq(v) - f_eq(u) = w rho [3 c.du + 4.5 (c.du)(c.(u+v)) - 1.5 du.(u+v)]
-      const double dx_ = double(Fs[0]) / dr, dy_ = double(Fs[1]) / dr, dz_ = double(Fs[2]) / dr;
-      const double sx = 2.0 * ux + dx_, sy = 2.0 * uy + dy_, sz = 2.0 * uz + dz_;
-      const double ds = dx_ * sx + dy_ * sy + dz_ * sz;
-#pragma unroll 1
-      for (int p = 0; p < NQ; ++p) {
-        const double fe = feq<double>(p, dr, ux, uy, uz, uu);
-        const double cd = double(kCx[p]) * dx_ + double(kCy[p]) * dy_ + double(kCz[p]) * dz_;
-        const double cs = double(kCx[p]) * sx + double(kCy[p]) * sy + double(kCz[p]) * sz;
-        const double src = wgt(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
-        const double fp = double(f[p * BLK]);
-        const double v = fp + ab * (fe - fp) + src;
-        const T tv = T(v);
-        if (!isfinite(tv)) c_nf += 1;
-        else if (tv < T(0)) c_neg += 1;
-        a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = tv;
-      }
+      a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
       if (record) {
         a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
         a.rec_iters[(int64_t)s * a.N + nd.g] = its;
       }
+    } else if (nd.live && record) {
+      a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
+      a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
+    }
+  }
+  // ---- counters: wave sums, one atomic per wave and counter
+  c_fb = wave_sum_u64(c_fb);
+  c_it = wave_sum_u64(c_it);
+  c_col = wave_sum_u64(c_col);
+  if (lane == 0) {
+    unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
+    if (c_fb) atomicAdd(cn + 0, c_fb);
+    if (c_it) atomicAdd(cn + 1, c_it);
+    if (c_col) atomicAdd(cn + 4, c_col);
+  }
+}
+
+// k_collide: at fluid nodes the Shan-Chen (Eq. sc) and electric (Eq.
+// force_el2) forces, then per component the pulled populations again (the
+// same loads and FP64 moments as k_alpha) and the update
+//   f* = f + ab (f_eq - f) + f_eq(rho, u + F/rho) - f_eq(rho, u)
+// (exact-difference source, Eq. add).  Inlet nodes are reset; the recorded
+// half-step velocity is stored on request.
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int record) {
+  Node nd;
+  decode(a, nd);
+  const int lane = threadIdx.x & 63;
+  unsigned long long c_neg = 0, c_nf = 0;
+  const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
+  const bool fl = nd.live && k == K_FLUID;
+  unsigned solid = 0u;  // neighbour p solid or outside (bit p)
+  F acc[C][3], wall[3] = {F(0), F(0), F(0)}, Fel[3] = {F(0), F(0), F(0)}, rt = F(1);
+#pragma unroll
+  for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
+  if (fl) {
+    // ---- Shan-Chen (Eq. sc) and electric (Eq. force_el2) forces
+    F gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
+    const F phic = a.phi[nd.g], e2c = a.e2[nd.g];
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+      const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+      const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
+      if (m < 0 || (a.type[gm] & 3) == K_SOLID) solid |= 1u << p;
+      if ((solid >> p) & 1u) {
+        wall[0] += F(wgt(p) * kCx[p]);
+        wall[1] += F(wgt(p) * kCy[p]);
+        wall[2] += F(wgt(p) * kCz[p]);
+      } else {
+        F ps[C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) ps[t] = a.psi[(int64_t)t * a.N + gm];
+#pragma unroll
+        for (int s = 0; s < C; ++s) {
+          F sp = F(0);
+#pragma unroll
+          for (int t = 0; t < C; ++t) sp += F(M.G[s][t]) * ps[t];
+          acc[s][0] += F(wgt(p)) * sp * F(kCx[p]);
+          acc[s][1] += F(wgt(p)) * sp * F(kCy[p]);
+          acc[s][2] += F(wgt(p)) * sp * F(kCz[p]);
+        }
+      }
+      const F vp = m >= 0 ? a.phi[gm] : phic;
+      const F ve = m >= 0 ? a.e2[gm] : e2c;
+      gp[0] += F(wgt(p) * kCx[p]) * vp;
+      gp[1] += F(wgt(p) * kCy[p]) * vp;
+      gp[2] += F(wgt(p) * kCz[p]) * vp;
+      ge[0] += F(wgt(p) * kCx[p]) * ve;
+      ge[1] += F(wgt(p) * kCy[p]) * ve;
+      ge[2] += F(wgt(p) * kCz[p]) * ve;
+    }
+    const F qn = a.q[nd.g];
+    const F rA = a.rho[nd.g];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const F E = F(nd.B.E[d]) - gp[d] / F(CS2);
+      Fel[d] = qn * E;
+      if (M.electrostriction) Fel[d] += F(0.5) * rA * (ge[d] / F(CS2));
+    }
+    rt = F(0);
+#pragma unroll
+    for (int s = 0; s < C; ++s) rt += a.rho[(int64_t)s * a.N + nd.g];
+  }
+  double mom[3] = {0.0, 0.0, 0.0}, drt = 0.0;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    if (!fl) continue;
+    // ---- pulled populations and their FP64 moments (as in k_alpha)
+    T f[NQ];
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) {
+      const int q = opp(p);
+      const bool bounce = (p != 0) && ((solid >> q) & 1u);
+      const int m = p ? nbr(nd.B, nd.x, nd.y, nd.z, kCx[q], kCy[q], kCz[q]) : nd.n;
+      f[p] = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g]
+                    : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + m];
+      const double dv = double(f[p]);
+      dr += dv;
+      jx += double(kCx[p]) * dv;
+      jy += double(kCy[p]) * dv;
+      jz += double(kCz[p]) * dv;
+    }
+    const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    drt += dr;
+    const F ps = a.psi[(int64_t)s * a.N + nd.g];
+    const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
+    F gw = F(0);  // wall neighbours carry the node's own psi (Eq. sc, wall sum)
+#pragma unroll
+    for (int t = 0; t < C; ++t) gw += F(M.Gw[s][t]) * a.psi[(int64_t)t * a.N + nd.g];
+    F Fs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - ps * gw * wall[d] + frac * Fel[d];
+    mom[0] += jx + 0.5 * double(Fs[0]);
+    mom[1] += jy + 0.5 * double(Fs[1]);
+    mom[2] += jz + 0.5 * double(Fs[2]);
+    const double ab = a.ab[(int64_t)s * a.N + nd.g];
+    // ---- exact-difference source (Eq. add): with v = u + F/rho,
+    // f_eq(v) - f_eq(u) = w rho [3 c.du + 4.5 (c.du)(c.(u+v)) - 1.5 du.(u+v)]
+    const double dx_ = double(Fs[0]) / dr, dy_ = double(Fs[1]) / dr, dz_ = double(Fs[2]) / dr;
+    const double sx = 2.0 * ux + dx_, sy = 2.0 * uy + dy_, sz = 2.0 * uz + dz_;
+    const double ds = dx_ * sx + dy_ * sy + dz_ * sz;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) {
+      const double fe = feq<double>(p, dr, ux, uy, uz, uu);
+      const double cd = double(kCx[p]) * dx_ + double(kCy[p]) * dy_ + double(kCz[p]) * dz_;
+      const double cs = double(kCx[p]) * sx + double(kCy[p]) * sy + double(kCz[p]) * sz;
+      const double src = wgt(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
+      const double fp = double(f[p]);
+      const double v = fp + ab * (fe - fp) + src;
+      const T tv = T(v);
+      if (!isfinite(tv)) c_nf += 1;
+      else if (tv < T(0)) c_neg += 1;
+      a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = tv;
     }
   }
   if (fl && record) {
@@ -526,7 +588,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
     a.rec_u[a.N + nd.g] = F(mom[1] / drt);
     a.rec_u[2 * a.N + nd.g] = F(mom[2] / drt);
   } else if (nd.live && record) {
-    // boundary and wall nodes: populations stay; recorded velocity sum j / sum rho
+    // boundary and wall nodes: recorded velocity sum j / sum rho of their populations
     double r = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
     if (k != K_SOLID) {
 #pragma unroll
@@ -543,29 +605,18 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_collide(Ptrs<T,
     a.rec_u[nd.g] = r > 0.0 ? F(m0 / r) : F(0);
     a.rec_u[a.N + nd.g] = r > 0.0 ? F(m1 / r) : F(0);
     a.rec_u[2 * a.N + nd.g] = r > 0.0 ? F(m2 / r) : F(0);
-#pragma unroll
-    for (int s = 0; s < C; ++s) {
-      a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
-      a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
-    }
   }
   if (nd.live && k == K_INLET) inlet_store<T, F, C>(a, M, nd);
   // ---- counters: wave sums, one atomic per wave and counter
-  c_fb = wave_sum_u64(c_fb);
-  c_it = wave_sum_u64(c_it);
   c_neg = wave_sum_u64(c_neg);
   c_nf = wave_sum_u64(c_nf);
-  c_col = wave_sum_u64(c_col);
   if (lane == 0) {
     unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
-    if (c_fb) atomicAdd(cn + 0, c_fb);
-    if (c_it) atomicAdd(cn + 1, c_it);
     if (c_neg) atomicAdd(cn + 2, c_neg);
     if (c_nf) {
       atomicAdd(cn + 3, c_nf);
       atomicOr(a.err, 1u);
     }
-    if (c_col) atomicAdd(cn + 4, c_col);
   }
 }
 

@@ -75,7 +75,7 @@ SYMBOLS = [
 ]
 TUNE_CANDIDATES = 9
 TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
-PHASES = ["density", "charge", "poisson", "efield", "collide"]
+PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
 

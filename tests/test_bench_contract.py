@@ -17,9 +17,12 @@ def test_more_than_one_gpu_is_refused():
 def test_algorithmic_bytes_per_node():
     sys.path.insert(0, ROOT)
     import bench
-    # 19 populations of 2 components read and written in FP32, plus psi of each
-    # component, phi, |E|^2, q, rho_A (FP32 field count) and the type byte
-    assert bench.collide_bytes_per_node(4, 2) == 2 * 2 * 19 * 4 + 6 * 4 + 1 == 329
-    assert bench.collide_bytes_per_node(8, 2) == 2 * 2 * 19 * 8 + 6 * 8 + 1
+    # k_alpha: 19 populations of 2 components read in FP32, alpha * beta of
+    # each component written in FP64, the type byte
+    assert bench.alpha_bytes_per_node(4, 2) == 2 * 19 * 4 + 2 * 8 + 1 == 169
+    # k_collide: populations read and written, alpha * beta read, psi of each
+    # component, phi, |E|^2, q and the component densities (FP64 fields), type
+    assert bench.collide_bytes_per_node(4, 8, 2) == 2 * 2 * 19 * 4 + 2 * 8 + 7 * 8 + 1 == 377
+    assert bench.collide_bytes_per_node(4, 4, 2) == 304 + 16 + 28 + 1
     # whole step with k SOR sweeps
     assert bench.step_bytes_per_node(4, 2, 8) == 304 + 40 + 128
