@@ -237,6 +237,37 @@ __device__ __forceinline__ double log1p_fast(double y) {
   return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * q + c * __builtin_amdgcn_rcp(t)));
 }
 
+// e^x for |x| < 700 to ~2 ulp: x = k ln2 + r with the same split of ln2 as
+// log1p_fast (k ln2_hi exact), |r| <= ln2/2, e^r by its Taylor series through
+// r^13 (first dropped term below 3e-18 relative), then the power of two.
+__device__ __forceinline__ double exp_fast(double x) {
+  const double k = rint(x * 1.44269504088896340736);
+  const double r = fma(-k, 1.90821492927058770002e-10, fma(-k, 6.93147180369123816490e-01, x));
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, int(k));
+}
+
+// (1 + q)^e for q >= 0, the Carreau factor: e^(e ln(1 + q)) in FP64 (no
+// rounding of 1 + q), the library pow in FP32.
+template <typename R>
+__device__ __forceinline__ R pow1p(R q, R e) {
+  if constexpr (sizeof(R) == 8) return exp_fast(e * log1p_fast(q));
+  else return pow(R(1) + q, e);
+}
+
 // phi(y) = (1+y) ln(1+y) - y given l = ln(1+y), cancellation-free: Taylor
 // series sum_{k>=2} (-1)^k y^k / (k(k-1)) through k = 15 for |y| < 1/16
 // (first dropped term below 2e-19 relative), the closed form elsewhere.
@@ -541,7 +572,7 @@ __device__ R shear_rate(R Pn, R rho, R alpha, R nu0, R ninf, R lam, R n) {
   for (int it = 0; it < 60; ++it) {
     const R lg = lam * g;
     const R s = R(1) + lg * lg;
-    const R e = pow(s, R(0.5) * (n - R(3)));  // s^((n-3)/2); s^((n-1)/2) = s * e
+    const R e = pow1p<R>(lg * lg, R(0.5) * (n - R(3)));  // s^((n-3)/2); s^((n-1)/2) = s * e
     const R nu = ninf + (nu0 - ninf) * s * e;
     const R h = rho * (R(2) * nu + R(CS2)) * g - alpha * Pn;
     if (h > R(0)) hi = g; else lo = g;

@@ -12,8 +12,10 @@
 //   k_sor x 2k     red-black SOR half sweeps
 //   (gauge)        zero-mean potential for boxes without Dirichlet nodes
 //   k_efield       |E|^2 with E = E_ext - grad phi
-//   k_collide      pull again, Shan-Chen + electric force, FP64 alpha Newton,
-//                  Carreau beta, exact-difference source, write f*
+//   k_alpha        (second stream, beside the kernels above) pull, FP64 alpha
+//                  Newton, Carreau beta -> alpha * beta
+//   k_collide      pull again, Shan-Chen + electric force, exact-difference
+//                  source, write f*
 #pragma once
 
 #include "elbm_device.h"
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         const R nf = R(nd.B.n_flow);
         const R gd = shear_rate<R>(Pn, R(dr), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
         const R lg = R(M.lam) * gd;
-        nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow(R(1) + lg * lg, R(0.5) * (nf - R(1))));
+        nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow1p<R>(lg * lg, R(0.5) * (nf - R(1))));
       }
       a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
       if (record) {

@@ -128,6 +128,25 @@ def test_ragged_multibox_all_terms_fp64(elbm):
         compare(lat, i, o, 1e-12)
 
 
+def test_poisson_odd_sweeps_small_boxes_fp64(elbm):
+    # The Poisson sweeps on boxes smaller than one 256-node block (periodic
+    # edges of 4 and 6, a bounded edge of 5), an odd sweep count and Dirichlet
+    # walls, against the oracle.  (Fields
+    # are compared relative to their largest value, so every box carries a
+    # field with an x component: a velocity that vanishes by symmetry would
+    # leave only rounding noise to compare.)
+    p = inputs.base_params(Q_b=0.02, Q_s=0.2, sor_sweeps=5, sor_omega=1.4)
+    b0 = inputs.droplet_box(4, 6, 10, 1.5, seed=21)
+    b0.info.update(E_ext=[1e-3, 1e-3, 0.0])
+    b1 = inputs.droplet_box(6, 6, 5, 1.5, seed=22, walls_z=True, phi_bottom=0.0, phi_top=-0.01)
+    b1.info.update(E_ext=[1e-3, 0.0, 0.0])
+    b2 = inputs.droplet_box(10, 4, 12, 2.0, seed=23)
+    b2.info.update(E_ext=[2e-3, 0.0, 1e-3])
+    lat, oras = run_both(elbm, p, [b0, b1, b2], "f64", 12, "tiny boxes, 5 sweeps")
+    for i, o in enumerate(oras):
+        compare(lat, i, o, 1e-12)
+
+
 def test_efield_walls_carreau_fp64(elbm):
     # Reduced geometry of the drop between electrodes: walls + Dirichlet planes, Carreau.
     wl = inputs.efield_drop(nx=16, ny=16, nz=32)
