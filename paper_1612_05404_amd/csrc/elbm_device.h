@@ -523,11 +523,23 @@ __device__ __forceinline__ bool features_from_x(const double *xs, float *z, doub
 }
 
 // Matrix 2-norm of a symmetric 3x3 (largest |eigenvalue|), cyclic Jacobi
-// rotations until the off-diagonal part is negligible at the type's precision.
+// rotations until the off-diagonal part is below 1e-12 of the diagonal
+// (squared: 1e-24; the eigenvalues then carry an error of second order in
+// it, far below rounding).  In FP64 the rotation (Rutishauser's form) uses
+// the refined hardware reciprocal and reciprocal square root instead of
+// divisions and square roots: a rotation accurate to ~1 ulp is orthogonal to
+// rounding, which is all the eigenvalues need.
+__device__ __forceinline__ double rsq_nr(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  r = r * fma(-h * r, r, 1.5);
+  return r * fma(-h * r, r, 1.5);
+}
+
 template <typename R>
 __device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
   R a[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
-  const R tiny = sizeof(R) == 8 ? R(1e-32) : R(1e-14);
+  const R tiny = sizeof(R) == 8 ? R(1e-24) : R(1e-14);
   for (int sweep = 0; sweep < 10; ++sweep) {
     const R off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
     const R diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
@@ -536,9 +548,20 @@ __device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
     for (int pq = 0; pq < 3; ++pq) {
       const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
       if (a[p][q] == R(0)) continue;
-      const R th = (a[q][q] - a[p][p]) / (R(2) * a[p][q]);
-      const R t = (th >= R(0) ? R(1) : R(-1)) / (fabs(th) + sqrt(th * th + R(1)));
-      const R c = R(1) / sqrt(t * t + R(1)), s = t * c;
+      R t, c;
+      if constexpr (sizeof(R) == 8) {
+        const double th = (a[q][q] - a[p][p]) * rcp_nr(2.0 * a[p][q]);
+        const double at = fabs(th);
+        // |th| beyond 1e100: t = 1/(2 th) to full precision, and th^2 would overflow
+        const double tm = at > 1e100 ? 0.5 * rcp_nr(at) : rcp_nr(at + (th * th + 1.0) * rsq_nr(th * th + 1.0));
+        t = th >= 0.0 ? tm : -tm;
+        c = rsq_nr(t * t + 1.0);
+      } else {
+        const R th = (a[q][q] - a[p][p]) / (R(2) * a[p][q]);
+        t = (th >= R(0) ? R(1) : R(-1)) / (fabs(th) + sqrt(th * th + R(1)));
+        c = R(1) / sqrt(t * t + R(1));
+      }
+      const R s = t * c;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const R akp = a[k][p], akq = a[k][q];
