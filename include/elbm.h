@@ -198,7 +198,7 @@ enum {
  * stream around each phase of each following step (a small overhead between
  * launches); enable == 0 stops and discards.  Host-side events only, no device
  * memory.  Without timing the alpha phase runs on a second stream of the
- * library, beside the density .. E-field phases; with timing every phase
+ * library, beside the Poisson and E-field phases; with timing every phase
  * runs in order on the bound stream. */
 elbm_status elbm_set_timing(elbm_ctx *ctx, int32_t enable);
 

@@ -235,11 +235,21 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     c->ev_used += per;
   }
   // k_alpha needs only the populations: without phase timing it runs on the
-  // second stream beside the field chain (density .. E), and k_collide waits
-  // for it; with timing everything runs in order on the bound stream.
+  // second stream beside the Poisson sweeps and the E field (forked there:
+  // beside the whole chain it slows the density and charge kernels more than
+  // it gains), and k_collide waits for it; with timing everything runs in
+  // order on the bound stream.
   const dim3 cgrid(c->tile ? (unsigned)c->ntiles[c->tile] : grid.x);
   const bool fork = !c->timing;
   hipStream_t as = fork ? c->aux : c->stream;
+  mark(c, ev, 0);
+  hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 1);
+  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
+  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M);
+  hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 2);
   if (fork) {
     HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
@@ -249,14 +259,6 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
       hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
     HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   }
-  mark(c, ev, 0);
-  hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
-  mark(c, ev, 1);
-  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
-  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
-  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M);
-  hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
-  mark(c, ev, 2);
   for (int sw = 0; sw < c->P.sor_sweeps; ++sw) {
     hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0);
     hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1);
