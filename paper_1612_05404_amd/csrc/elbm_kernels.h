@@ -426,10 +426,12 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
       using R = F;
       double nu = M.nu0;
       if (M.carreau) {
+        // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
+        // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
         double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
 #pragma unroll 1
         for (int p = 0; p < NQ; ++p) {
-          const double d = double(f[p * BLK]) - feq<double>(p, dr, ux, uy, uz, uu);
+          const double d = double(f[p * BLK]);
           P00 += d * double(kCx[p] * kCx[p]);
           P11 += d * double(kCy[p] * kCy[p]);
           P22 += d * double(kCz[p] * kCz[p]);
@@ -437,6 +439,12 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
           P02 += d * double(kCx[p] * kCz[p]);
           P12 += d * double(kCy[p] * kCz[p]);
         }
+        P00 -= dr * (CS2 + ux * ux);
+        P11 -= dr * (CS2 + uy * uy);
+        P22 -= dr * (CS2 + uz * uz);
+        P01 -= dr * (ux * uy);
+        P02 -= dr * (ux * uz);
+        P12 -= dr * (uy * uz);
         const R Pn = sym3_norm2<R>(R(P00), R(P11), R(P22), R(P01), R(P02), R(P12));
         const R nf = R(nd.B.n_flow);
         const R gd = shear_rate<R>(Pn, R(dr), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
