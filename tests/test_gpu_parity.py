@@ -298,6 +298,36 @@ def test_graph_replay_matches_direct_launches(elbm):
     assert g.diagnostics(0)["n_collisions"] == d.diagnostics(0)["n_collisions"]
 
 
+def test_alpha_stream_order_does_not_change_results(elbm):
+    # k_alpha runs on the library's second stream beside the Poisson sweeps,
+    # or in order on one stream when phase timing is on: it reads only the
+    # populations, so both give the same step bit for bit (learned starter
+    # included), graph-replayed or launched directly.
+    wl = inputs.efield_drop(nx=16, ny=16, nz=32)
+    _say("[gpu] two streams vs one stream (phase timing), efield 16x16x32 f32, series and learned starters")
+    from paper_1612_05404_amd import learned
+    for guess in ("series", "mlp"):
+        a = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess=guess)
+        b = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess=guess)
+        if guess == "mlp":
+            w = learned.load_weights()
+            a.mlp_set_weights(w)
+            b.mlp_set_weights(w)
+        b.set_timing(True)
+        for rep in range(3):
+            a.step(7, record=True)
+            b.step(7, record=True)
+            a.sync()
+            b.sync()
+            assert np.array_equal(a.get_populations(0), b.get_populations(0)), (guess, rep)
+            assert np.array_equal(a.read_alpha(0)[0], b.read_alpha(0)[0]), (guess, rep)
+        ph = b.timing()
+        assert ph["steps"] == 21 and ph["alpha"] > 0 and ph["collide"] > 0
+        assert a.diagnostics(0)["mean_newton_iters"] == b.diagnostics(0)["mean_newton_iters"]
+        a.close()
+        b.close()
+
+
 def test_nonfinite_is_reported(elbm):
     # A NaN planted from the host propagates and sets the sticky error word.
     wl = inputs.drop32(n=16)
