@@ -42,9 +42,9 @@ ROOF_AT, ROOF_STEPS = 250, 16  # the roofline window: steps 251..266
 # and the HBM bytes of one launch of each kernel (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives for the same
 # counters).  None: not counted for the current kernels.
-ALPHA_FP64_FLOP_PER_NODE = 11874
-ALPHA_TRAFFIC_BYTES = 369_141_859
-COLLIDE_TRAFFIC_BYTES = 220_058_249
+ALPHA_FP64_FLOP_PER_NODE = 10954
+ALPHA_TRAFFIC_BYTES = 369_098_404
+COLLIDE_TRAFFIC_BYTES = 220_009_658
 
 
 def alpha_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
