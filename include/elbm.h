@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 1u
+#define ELBM_ABI_VERSION 2u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing */
 
 typedef struct elbm_ctx elbm_ctx;
 

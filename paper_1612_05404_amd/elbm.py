@@ -78,6 +78,7 @@ TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
+ABI_VERSION = 2  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -91,6 +92,9 @@ def load(path: str = LIB_PATH):
     vp, i32, dp = ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double)
     L.elbm_abi_version.restype = ct.c_uint32
     L.elbm_abi_version.argtypes = []
+    if L.elbm_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} has ABI version {L.elbm_abi_version()}, this binding needs {ABI_VERSION}; "
+                          "rebuild with __graft_entry__.build()")
     L.elbm_create.argtypes = [ct.POINTER(elbm_params), ct.POINTER(elbm_box), i32, ct.POINTER(vp)]
     L.elbm_required_bytes.argtypes = [vp, ct.POINTER(ct.c_size_t)]
     L.elbm_bind.argtypes = [vp, vp, ct.c_size_t, vp]

@@ -36,7 +36,8 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.elbm_abi_version() == 1
+    from paper_1612_05404_amd import elbm
+    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 2
 
 
 def _params(**kw):
