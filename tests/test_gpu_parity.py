@@ -56,10 +56,13 @@ def compare(lat, i, o, tol, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi", "q"
     return errs
 
 
-def run_both(elbm, params, boxes, dtype, steps, name):
+def run_both(elbm, params, boxes, dtype, steps, name, launch=None, guess=None):
     import oracle as ora
-    _say(f"[gpu parity] {name}: dtype={dtype} steps={steps} boxes={[(b.nx, b.ny, b.nz) for b in boxes]}")
-    lat = elbm.Lattice(params, boxes, dtype)
+    _say(f"[gpu parity] {name}: dtype={dtype} steps={steps} boxes={[(b.nx, b.ny, b.nz) for b in boxes]}"
+         f" launch={launch} guess={guess}")
+    lat = elbm.Lattice(params, boxes, dtype) if guess is None else elbm.Lattice(params, boxes, dtype, alpha_guess=guess)
+    if launch is not None:
+        lat.set_launch(*launch)
     lat.step(steps, record=True)
     lat.sync()
     oras = []
@@ -202,9 +205,12 @@ def test_efield_fp32all_100_steps(elbm):
 
 
 def test_efield_full_size_fp32(elbm):
-    # The benchmark's workload at its full size (64x64x128, FP32), 100 steps.
+    # The benchmark's workload at its full size (64x64x128, FP32), 100 steps,
+    # in the launch mapping and with the starter the benchmark times (8x4x8
+    # bricks for k_alpha, 4-step graphs, k_alpha beside the sweeps, series root).
     wl = inputs.efield_drop()
-    lat, (o,) = run_both(elbm, wl.params, wl.boxes, "f32", 100, "efield 64x64x128 f32")
+    lat, (o,) = run_both(elbm, wl.params, wl.boxes, "f32", 100, "efield 64x64x128 f32", launch=(0, 4, 2),
+                         guess="series")
     check_fp32(lat, o, wl.params, wl.boxes[0], 100)
 
 
