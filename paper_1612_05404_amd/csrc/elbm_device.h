@@ -54,7 +54,7 @@ constexpr int NCNT = 8;
 template <typename T, typename F>
 struct Ptrs {
   T *fa, *fb;           // populations: read fa, write fb
-  F *rho, *psi, *grad, *bulk, *surf, *q, *phi, *rhs, *e2;  // grad: unit normal [3], |grad rho_A|^2
+  F *rho, *psi, *grad, *bulk, *surf, *q, *phi, *rhs, *e2;  // psi [N][C]; grad: unit normal [3], |grad rho_A|^2
   F *rec_u;
   const F *ubc;         // [3][N] inlet velocity (read at inlet nodes)
   double *ab;           // [C][N] alpha * beta of the step's collision

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
       }
     }
     a.rho[(int64_t)s * a.N + nd.g] = r;
-    a.psi[(int64_t)s * a.N + nd.g] = (k == K_SOLID) ? F(0) : -expm1(-r);
+    a.psi[nd.g * C + s] = (k == K_SOLID) ? F(0) : -expm1(-r);  // [N][C]: one load per neighbour in k_collide
   }
 }
 
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       } else {
         F ps[C];
 #pragma unroll
-        for (int t = 0; t < C; ++t) ps[t] = a.psi[(int64_t)t * a.N + gm];
+        for (int t = 0; t < C; ++t) ps[t] = a.psi[gm * C + t];
 #pragma unroll
         for (int s = 0; s < C; ++s) {
           F sp = F(0);
@@ -562,11 +562,11 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
     const double uu = ux * ux + uy * uy + uz * uz;
     drt += dr;
-    const F ps = a.psi[(int64_t)s * a.N + nd.g];
+    const F ps = a.psi[nd.g * C + s];
     const F frac = a.rho[(int64_t)s * a.N + nd.g] / rt;
     F gw = F(0);  // wall neighbours carry the node's own psi (Eq. sc, wall sum)
 #pragma unroll
-    for (int t = 0; t < C; ++t) gw += F(M.Gw[s][t]) * a.psi[(int64_t)t * a.N + nd.g];
+    for (int t = 0; t < C; ++t) gw += F(M.Gw[s][t]) * a.psi[nd.g * C + t];
     F Fs[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) Fs[d] = -ps * acc[s][d] - ps * gw * wall[d] + frac * Fel[d];
