@@ -42,7 +42,7 @@ struct elbm_ctx {
   int nblocks = 0;
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
-  size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_reca,
+  size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_nbm, o_reca,
       o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_scal, o_cnt, o_err, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
@@ -154,6 +154,7 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.rec_u = (F *)(b + c->o_recu);
   a.ubc = (const F *)(b + c->o_ubc);
   a.ab = (double *)(b + c->o_ab);
+  a.nbm = (const uint32_t *)(b + c->o_nbm);
   a.rec_alpha = (double *)(b + c->o_reca);
   a.rec_iters = (int32_t *)(b + c->o_reci);
   a.type = (uint8_t *)(b + c->o_type);
@@ -360,6 +361,10 @@ elbm_status set_box_impl(elbm_ctx *c, int box, const uint8_t *type, const double
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+  // neighbour masks (static geometry), for every box: cheap, and boxes set later redo them
+  hipLaunchKernelGGL((k_neighbour_mask<T, F>), dim3(c->nblocks), blk, 0, c->stream, a,
+                     (uint32_t *)(c->base + c->o_nbm));
+  HIPCHK(c, hipGetLastError());
   // inlet velocity, kept for the step's inlet update
   for (int d = 0; d < 3; ++d) {
     F *dst = (F *)(c->base + c->o_ubc) + (size_t)d * c->Ntot + B.off;
@@ -531,6 +536,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_recu = take(3 * (size_t)N * e);
   c->o_ubc = take(3 * (size_t)N * e);
   c->o_ab = take((size_t)C * N * 8);
+  c->o_nbm = take((size_t)N * 4);
   c->o_reca = take((size_t)C * N * 8);
   c->o_reci = take((size_t)C * N * 4);
   c->o_type = take((size_t)N);

@@ -61,6 +61,7 @@ struct Ptrs {
   double *rec_alpha;
   int32_t *rec_iters;
   uint8_t *type;
+  const uint32_t *nbm;   // [N] bit p: neighbour r + c_p solid or outside the box (static geometry)
   const BoxDev *boxes;
   const int32_t *block_box;
   double *partials;     // [nblocks][4]

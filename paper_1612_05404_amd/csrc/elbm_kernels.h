@@ -23,6 +23,23 @@
 
 namespace elbm {
 
+// Neighbour mask of every node (the geometry is fixed once a box is set):
+// bit p set when r + c_p is a solid node or outside a bounded box.  The
+// kernels read it instead of 18 neighbour type bytes.
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_neighbour_mask(Ptrs<T, F> a, uint32_t *nbm) {
+  Node nd;
+  decode(a, nd);
+  if (!nd.live) return;
+  uint32_t msk = 0u;
+#pragma unroll
+  for (int p = 1; p < NQ; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+    if (m < 0 || (a.type[nd.B.off + m] & 3) == K_SOLID) msk |= 1u << p;
+  }
+  nbm[nd.g] = msk;
+}
+
 // Streaming (left side of Eq. lattice-b) by pulling + densities and the
 // Shan-Chen pseudo-potential psi = 1 - exp(-rho) (rho_0 = 1).  Sums run in
 // the field type F in the order p = 0..18.
@@ -32,15 +49,15 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
   decode(a, nd);
   if (!nd.live) return;
   const int k = a.type[nd.g] & 3;
+  const uint32_t msk = a.nbm[nd.g];  // the source of p is the neighbour in direction opp(p)
   int src[NQ];
   bool bb[NQ];
   src[0] = nd.n;
   bb[0] = false;
 #pragma unroll
   for (int p = 1; p < NQ; ++p) {
-    const int m = nbr(nd.B, nd.x, nd.y, nd.z, -kCx[p], -kCy[p], -kCz[p]);
-    bb[p] = (m < 0) || ((a.type[nd.B.off + m] & 3) == K_SOLID);
-    src[p] = m;
+    src[p] = nbr(nd.B, nd.x, nd.y, nd.z, -kCx[p], -kCy[p], -kCz[p]);
+    bb[p] = ((msk >> opp(p)) & 1u) || src[p] < 0;
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
@@ -72,11 +89,12 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
   F g0 = F(0), g1 = F(0), g2 = F(0);
   if ((a.type[nd.g] & 3) != K_SOLID) {
     const F c = a.rho[nd.g];
+    const uint32_t msk = a.nbm[nd.g];
 #pragma unroll
     for (int p = 1; p < NQ; ++p) {
       const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
       F v = c;
-      if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) v = a.rho[nd.B.off + m];
+      if (m >= 0 && !((msk >> p) & 1u)) v = a.rho[nd.B.off + m];
       g0 += F(wgt(p) * kCx[p]) * v;
       g1 += F(wgt(p) * kCy[p]) * v;
       g2 += F(wgt(p) * kCz[p]) * v;
@@ -109,12 +127,13 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
     F bulk = F(0), surf = F(0);
     if ((tt & 3) != K_SOLID) {
       const F c0 = a.grad[nd.g], c1 = a.grad[a.N + nd.g], c2 = a.grad[2 * a.N + nd.g];
+      const uint32_t msk = a.nbm[nd.g];
       F div = F(0);
 #pragma unroll
       for (int p = 1; p < NQ; ++p) {
         const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
         F n0 = c0, n1 = c1, n2 = c2;
-        if (m >= 0 && (a.type[nd.B.off + m] & 3) != K_SOLID) {
+        if (m >= 0 && !((msk >> p) & 1u)) {
           const int64_t gm = nd.B.off + m;
           n0 = a.grad[gm];
           n1 = a.grad[a.N + gm];
@@ -359,10 +378,11 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
   if (fl) {
     // ---- neighbours: local index, solid-or-outside flag
     nl[0] = nd.n;
+    solid = a.nbm[nd.g];
 #pragma unroll
     for (int p = 1; p < NQ; ++p) {
       nl[p] = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
-      if (nl[p] < 0 || (a.type[nd.B.off + nl[p]] & 3) == K_SOLID) solid |= 1u << p;
+      if (nl[p] < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
     }
   }
   T *f = lds_f + threadIdx.x;
@@ -487,7 +507,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
   unsigned long long c_neg = 0, c_nf = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
   const bool fl = nd.live && k == K_FLUID;
-  unsigned solid = 0u;  // neighbour p solid or outside (bit p)
+  unsigned solid = fl ? a.nbm[nd.g] : 0u;  // neighbour p solid or outside (bit p)
   F acc[C][3], wall[3] = {F(0), F(0), F(0)}, Fel[3] = {F(0), F(0), F(0)}, rt = F(1);
 #pragma unroll
   for (int s = 0; s < C; ++s) acc[s][0] = acc[s][1] = acc[s][2] = F(0);
@@ -499,7 +519,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     for (int p = 1; p < NQ; ++p) {
       const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
       const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
-      if (m < 0 || (a.type[gm] & 3) == K_SOLID) solid |= 1u << p;
+      if (m < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
       if ((solid >> p) & 1u) {
         wall[0] += F(wgt(p) * kCx[p]);
         wall[1] += F(wgt(p) * kCy[p]);
