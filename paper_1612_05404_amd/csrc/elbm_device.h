@@ -87,6 +87,12 @@ __host__ __device__ constexpr int tile_dim(int shape, int axis) {
        : shape == 3 ? (axis == 0 ? 4 : axis == 1 ? 4 : 16) : 0;
 }
 
+// Kernels of the Poisson branch (SOR sweeps, gauge, E field) run beside
+// k_alpha, which keeps two long FP64-bound waves on every SIMD. Raising their
+// waves' instruction-issue priority lets the short, latency-bound sweeps
+// issue first; it changes no result.
+__device__ __forceinline__ void poisson_branch_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // ------------------------------------------------------------ node decode
 struct Node {
   BoxDev B;
