@@ -43,8 +43,8 @@ ROOF_AT, ROOF_STEPS = 250, 16  # the roofline window: steps 251..266
 # WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives for the same
 # counters).  None: not counted for the current kernels.
 ALPHA_FP64_FLOP_PER_NODE = 10954
-ALPHA_TRAFFIC_BYTES = 377_711_191
-COLLIDE_TRAFFIC_BYTES = 216_281_305
+ALPHA_TRAFFIC_BYTES = 377_760_888
+COLLIDE_TRAFFIC_BYTES = 216_270_021
 
 
 def alpha_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -190,7 +190,8 @@ def main():
     ap.add_argument("--no-jet", action="store_true", help="skip the jet leg (three starters)")
     ap.add_argument("--jet-warmup", type=int, default=200)
     ap.add_argument("--jet-steps", type=int, default=100)
-    ap.add_argument("--launch", default=None, help="launch mapping remap,graph_steps,tile (skips the autotuner)")
+    ap.add_argument("--launch", default=None,
+                    help="launch mapping remap,graph_steps,tile,sweep_priority (skips the autotuner)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the collision's roofline window (for counter runs)")
     args = ap.parse_args()
@@ -231,8 +232,8 @@ def main():
 
     def tuned_launch(mode):
         if args.launch:
-            r, g, t = (int(v) for v in args.launch.split(","))
-            return {"xcd_remap": r, "graph_steps": g, "tile": t}
+            r, g, t, p = (int(v) for v in args.launch.split(","))
+            return {"xcd_remap": r, "graph_steps": g, "tile": t, "sweep_priority": p}
         # tuned on a throw-away instance: the timed runs start from the initial state
         lat = make(mode)
         lat.step(args.warmup, record=False)

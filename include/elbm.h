@@ -42,7 +42,8 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 2u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing */
+#define ELBM_ABI_VERSION 3u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
+                                 3: sweep_priority in elbm_launch */
 
 typedef struct elbm_ctx elbm_ctx;
 
@@ -255,27 +256,33 @@ elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dT
  * (a 64-thread wave is a run along x), 1 = 8x8x4 nodes (waves 8x8x1),
  * 2 = 8x4x8 (waves 8x4x2), 3 = 4x4x16 (waves 4x4x4): 3-D waves gather the
  * nodes whose alpha needs many Newton updates (at interfaces) into fewer
- * waves.  None changes any result: per-node arithmetic and the order of
- * every reduction are the same under all mappings. */
+ * waves.  sweep_priority: 1 raises the instruction-issue priority of the
+ * waves of the Poisson branch (SOR sweeps, gauge, E field), which runs beside
+ * the alpha kernel on the second stream: it helps when that branch is the
+ * longer of the two, 0 (hardware default) when alpha is.  None changes any
+ * result: per-node arithmetic and the order of every reduction are the same
+ * under all mappings. */
 typedef struct elbm_launch {
   int32_t xcd_remap;
   int32_t graph_steps;
   int32_t tile;
+  int32_t sweep_priority;
 } elbm_launch;
-#define ELBM_TUNE_CANDIDATES 9
+#define ELBM_TUNE_CANDIDATES 11
 /* Sets / reads the launch mapping (synchronises the bound stream; drops the
  * captured graphs). */
 elbm_status elbm_set_launch(elbm_ctx *ctx, const elbm_launch *launch);
 elbm_status elbm_get_launch(const elbm_ctx *ctx, elbm_launch *launch);
-/* Chooses the mapping in three passes, each timing its candidates over
+/* Chooses the mapping in four passes, each timing its candidates over
  * steps_per_trial steps (rounded up to a multiple of 16) with HIP events on
  * the bound stream, in two rounds (forward, then reverse order; a
  * candidate's time is the mean of its two rounds), and keeping the fastest for the
- * next pass: tile 0..3 (with xcd_remap 0, graph_steps 2), then xcd_remap
- * 0, 1, then graph_steps 2, 4, 8.  best (may be NULL) receives the result;
+ * next pass: tile 0..3 (with xcd_remap 0, graph_steps 2, sweep_priority
+ * 0), then xcd_remap 0, 1, then sweep_priority 0, 1, then graph_steps 2, 4,
+ * 8.  best (may be NULL) receives the result;
  * ms_per_step [ELBM_TUNE_CANDIDATES] (may be NULL) each candidate's ms per
  * step in that order.  The trial steps are ordinary steps: the state
- * advances by 18 trial + 52 steps (each of the 18 trials first runs one
+ * advances by 22 trial + 60 steps (each of the 22 trials first runs one
  * graph's worth of steps to capture it).
  * Synchronous; phase timing must be off. */
 elbm_status elbm_autotune(elbm_ctx *ctx, int32_t steps_per_trial, elbm_launch *best, double *ms_per_step);

@@ -66,6 +66,7 @@ struct elbm_ctx {
   // block tile shape of the collision (0: linear)
   int remap = 0;
   int graph_steps = 2;
+  int prio = 0;  // issue priority of the Poisson-branch waves (0/1)
   int tile = 0;
   // per tile shape: tile -> box table, per-box tile counts, tiles in all
   std::vector<int32_t> tile_box[NTILE_SHAPES];
@@ -167,6 +168,7 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.N = c->Ntot;
   a.nblocks = c->nblocks;
   a.remap = c->remap;
+  a.prio = c->prio;
   a.tile_box = (const int32_t *)(b + c->o_tbox[c->tile]);
   a.box_tiles = (const int4 *)(b + c->o_btiles[c->tile]);
   a.tx = tile_dim(c->tile, 0);
@@ -266,7 +268,7 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   }
   if (c->any_gauge) {
     hipLaunchKernelGGL((k_phi_partials<T, F>), grid, blk, 0, c->stream, a);
-    hipLaunchKernelGGL(k_phi_mean, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal);
+    hipLaunchKernelGGL(k_phi_mean, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, a.prio);
     hipLaunchKernelGGL((k_phi_sub<T, F>), grid, blk, 0, c->stream, a);
   }
   mark(c, ev, 3);
@@ -652,10 +654,12 @@ elbm_status elbm_set_launch(elbm_ctx *c, const elbm_launch *l) {
   if (l->graph_steps < 2 || l->graph_steps > 64 || (l->graph_steps & 1))
     return fail(c, ELBM_EINVAL, "graph_steps must be even, 2..64");
   if (l->tile < 0 || l->tile >= NTILE_SHAPES) return fail(c, ELBM_EINVAL, "tile must be 0..3");
+  if (l->sweep_priority != 0 && l->sweep_priority != 1) return fail(c, ELBM_EINVAL, "sweep_priority must be 0 or 1");
   if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
   c->remap = l->xcd_remap;
   c->graph_steps = l->graph_steps;
   c->tile = l->tile;
+  c->prio = l->sweep_priority;
   c->drop_graphs();  // kernel arguments and step counts are baked into the graphs
   return ELBM_OK;
 }
@@ -665,6 +669,7 @@ elbm_status elbm_get_launch(const elbm_ctx *c, elbm_launch *l) {
   l->xcd_remap = c->remap;
   l->graph_steps = c->graph_steps;
   l->tile = c->tile;
+  l->sweep_priority = c->prio;
   return ELBM_OK;
 }
 
@@ -695,18 +700,19 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  const elbm_launch keep{c->remap, c->graph_steps, c->tile};
-  elbm_launch cur{0, 2, 0};
+  const elbm_launch keep{c->remap, c->graph_steps, c->tile, c->prio};
+  elbm_launch cur{0, 2, 0, 0};
   elbm_status st = ELBM_OK;
-  // three passes, each fixing one knob with the winners of the earlier ones:
-  // tile shape (4), XCD order (2), graph length (3); within a pass two
+  // four passes, each fixing one knob with the winners of the earlier ones:
+  // tile shape (4), XCD order (2), Poisson-branch priority (2), graph length
+  // (3; last, so that every earlier trial captures 2 steps); within a pass two
   // rounds, forward then reverse order, and a candidate's time is the mean of
   // its two: a state that drifts linearly during the trials (an initial
   // transient) then favours no candidate
   static const int kSteps[3] = {2, 4, 8};
   int slot = 0;
-  for (int pass = 0; pass < 3 && !st; ++pass) {
-    const int n = pass == 0 ? NTILE_SHAPES : pass == 1 ? 2 : 3;
+  for (int pass = 0; pass < 4 && !st; ++pass) {
+    const int n = pass == 0 ? NTILE_SHAPES : pass == 3 ? 3 : 2;
     double per[NTILE_SHAPES];
     for (int k = 0; k < n; ++k) per[k] = 0.0;
     for (int t = 0; t < 2 * n && !st; ++t) {
@@ -714,6 +720,7 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
       elbm_launch l = cur;
       if (pass == 0) l.tile = k;
       else if (pass == 1) l.xcd_remap = k;
+      else if (pass == 2) l.sweep_priority = k;
       else l.graph_steps = kSteps[k];
       double ms = 0.0;
       st = time_launch(c, l, trial, e0, e1, &ms);
@@ -728,6 +735,7 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
     slot += n;
     if (pass == 0) cur.tile = kb;
     else if (pass == 1) cur.xcd_remap = kb;
+    else if (pass == 2) cur.sweep_priority = kb;
     else cur.graph_steps = kSteps[kb];
   }
   (void)hipEventDestroy(e0);

@@ -71,6 +71,7 @@ struct Ptrs {
   int64_t N;            // arena nodes (plane stride)
   int32_t nblocks;      // node blocks of one launch
   int32_t remap;        // 1: XCD-aware block order
+  int32_t prio;         // 1: Poisson-branch waves at raised issue priority
   // block tiles of the collision (tx = 0: 256 consecutive nodes per block)
   const int32_t *tile_box;  // [ntiles] box of each tile
   const int4 *box_tiles;    // [nboxes] first tile, tiles along x, y, z
@@ -88,10 +89,13 @@ __host__ __device__ constexpr int tile_dim(int shape, int axis) {
 }
 
 // Kernels of the Poisson branch (SOR sweeps, gauge, E field) run beside
-// k_alpha, which keeps two long FP64-bound waves on every SIMD. Raising their
-// waves' instruction-issue priority lets the short, latency-bound sweeps
-// issue first; it changes no result.
-__device__ __forceinline__ void poisson_branch_priority() { __builtin_amdgcn_s_setprio(3); }
+// k_alpha, which keeps two long FP64-bound waves on every SIMD. With prio set
+// their waves get a higher instruction-issue priority, so that the short,
+// latency-bound sweeps issue first (worth it where that branch is the longer
+// one); it changes no result.
+__device__ __forceinline__ void poisson_branch_priority(int prio) {
+  if (prio) __builtin_amdgcn_s_setprio(3);
+}
 
 // ------------------------------------------------------------ node decode
 struct Node {

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
 // trip less); faces leaving the box are skipped.
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
-  poisson_branch_priority();
+  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
   if (!nd.live) return;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
 // Zero-mean gauge of the potential for boxes without Dirichlet nodes.
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
-  poisson_branch_priority();
+  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
   double acc[1] = {nd.live ? double(a.phi[nd.g]) : 0.0};
@@ -266,8 +266,8 @@ __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
 }
 
 __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const double *partials,
-                                                  double *scal) {
-  poisson_branch_priority();
+                                                  double *scal, int prio) {
+  poisson_branch_priority(prio);
   const BoxDev B = boxes[blockIdx.x];
   double acc[1] = {0.0};
   for (int i = threadIdx.x; i < B.nblocks; i += BLK) acc[0] += partials[(int64_t)(B.first_block + i) * 4];
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const dou
 
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
-  poisson_branch_priority();
+  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
   if (!nd.live || nd.B.has_dirichlet) return;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
 // takes the centre value, wall nodes carry their fixed potential).
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
-  poisson_branch_priority();
+  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
   if (!nd.live) return;

@@ -52,7 +52,8 @@ class elbm_box(ct.Structure):
 
 
 class elbm_launch(ct.Structure):
-    _fields_ = [("xcd_remap", ct.c_int32), ("graph_steps", ct.c_int32), ("tile", ct.c_int32)]
+    _fields_ = [("xcd_remap", ct.c_int32), ("graph_steps", ct.c_int32), ("tile", ct.c_int32),
+                ("sweep_priority", ct.c_int32)]
 
 
 class elbm_diag(ct.Structure):
@@ -73,12 +74,12 @@ SYMBOLS = [
     "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_train", "elbm_alpha_samples", "elbm_set_launch",
     "elbm_get_launch", "elbm_autotune", "elbm_last_error", "elbm_destroy",
 ]
-TUNE_CANDIDATES = 9
+TUNE_CANDIDATES = 11
 TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
-ABI_VERSION = 2  # include/elbm.h ELBM_ABI_VERSION
+ABI_VERSION = 3  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -377,23 +378,29 @@ class Lattice:
         return feat, tgt, scl, val
 
     # ---------------------------------------------------- launch mapping
-    def set_launch(self, xcd_remap: int, graph_steps: int, tile: int = 0):
-        l = elbm_launch(int(xcd_remap), int(graph_steps), int(tile))
+    def set_launch(self, xcd_remap: int, graph_steps: int, tile: int = 0, sweep_priority: int = 0):
+        l = elbm_launch(int(xcd_remap), int(graph_steps), int(tile), int(sweep_priority))
         self._check(self.L.elbm_set_launch(self.h, ct.byref(l)))
+
+    @staticmethod
+    def _launch_dict(l) -> dict:
+        return {"xcd_remap": l.xcd_remap, "graph_steps": l.graph_steps, "tile": l.tile,
+                "sweep_priority": l.sweep_priority}
 
     def get_launch(self) -> dict:
         l = elbm_launch()
         self._check(self.L.elbm_get_launch(self.h, ct.byref(l)))
-        return {"xcd_remap": l.xcd_remap, "graph_steps": l.graph_steps, "tile": l.tile}
+        return self._launch_dict(l)
 
     def autotune(self, steps_per_trial: int = 32):
-        """Chooses the launch mapping in three timed passes (collision tile
-        0..3, then XCD order 0, 1, then graph length 2, 4, 8); returns it and
-        each candidate's ms per step in that order.  The trial steps advance
-        the state like ordinary steps (18 trials + 52 in all)."""
+        """Chooses the launch mapping in four timed passes (collision tile
+        0..3, then XCD order 0, 1, then Poisson-branch priority 0, 1, then
+        graph length 2, 4, 8); returns it and each candidate's ms per step in
+        that order.  The trial steps advance the state like ordinary steps
+        (22 trials + 60 in all)."""
         import torch
         best = elbm_launch()
         ms = np.zeros(TUNE_CANDIDATES)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(self.L.elbm_autotune(self.h, int(steps_per_trial), ct.byref(best), ms.ctypes.data))
-        return {"xcd_remap": best.xcd_remap, "graph_steps": best.graph_steps, "tile": best.tile}, ms
+        return self._launch_dict(best), ms

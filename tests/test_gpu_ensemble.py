@@ -59,20 +59,21 @@ def test_launch_mappings_give_identical_results(elbm):
     wl = inputs.ensemble(nboxes=5, edges=(24, 32, 48))
     _say("[gpu ensemble] launch mappings, 5 boxes f32, 24 steps")
     ref = None
-    for remap, gs, tile in ((0, 2, 0), (1, 2, 0), (0, 8, 1), (1, 4, 2), (0, 2, 3), (1, 8, 3)):
+    for remap, gs, tile, prio in ((0, 2, 0, 0), (1, 2, 0, 1), (0, 8, 1, 0), (1, 4, 2, 1), (0, 2, 3, 1),
+                                  (1, 8, 3, 0)):
         lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-        lat.set_launch(remap, gs, tile)
-        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs, "tile": tile}
+        lat.set_launch(remap, gs, tile, prio)
+        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs, "tile": tile, "sweep_priority": prio}
         lat.step(24, record=True)
         got = [_fields(lat, i) + (lat.read_alpha(i)[0],) for i in range(len(wl.boxes))]
         if ref is None:
             ref = got
         else:
-            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs, tile)
+            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs, tile, prio)
         lat.close()
     lat = elbm.Lattice(wl.params, wl.boxes, "f32")
     try:
-        for bad in ((0, 3, 0), (2, 2, 0), (0, 2, 4)):
+        for bad in ((0, 3, 0), (2, 2, 0), (0, 2, 4), (0, 2, 0, 2)):
             with pytest.raises(elbm.ElbmError):
                 lat.set_launch(*bad)
     finally:
@@ -133,12 +134,15 @@ def test_autotune_keeps_results(elbm):
     _say(f"    best {best}; ms/step per candidate {np.round(ms, 4).tolist()}")
     assert np.all(np.isfinite(ms)) and np.all(ms > 0)
     assert best == a.get_launch()
-    # passes: tile 0..3, then XCD order 0..1, then graph length 2, 4, 8
+    # passes: tile 0..3, then XCD order 0..1, then Poisson-branch priority
+    # 0..1, then graph length 2, 4, 8
+    assert len(ms) == 11
     assert ms[best["tile"]] == ms[:4].min()
     assert ms[4 + best["xcd_remap"]] == ms[4:6].min()
-    assert ms[6 + {2: 0, 4: 1, 8: 2}[best["graph_steps"]]] == ms[6:].min()
+    assert ms[6 + best["sweep_priority"]] == ms[6:8].min()
+    assert ms[8 + {2: 0, 4: 1, 8: 2}[best["graph_steps"]]] == ms[8:].min()
     b = elbm.Lattice(wl.params, wl.boxes, "f32")
-    b.step(18 * 16 + 52, record=False)
+    b.step(22 * 16 + 60, record=False)
     a.step(1, record=True)
     b.step(1, record=True)
     for i in range(len(wl.boxes)):

@@ -207,9 +207,10 @@ def test_efield_fp32all_100_steps(elbm):
 def test_efield_full_size_fp32(elbm):
     # The benchmark's workload at its full size (64x64x128, FP32), 100 steps,
     # in the launch mapping and with the starter the benchmark times (8x4x8
-    # bricks for k_alpha, 4-step graphs, k_alpha beside the sweeps, series root).
+    # bricks for k_alpha, 4-step graphs, k_alpha beside the sweeps with the
+    # sweeps' waves at raised priority, series root).
     wl = inputs.efield_drop()
-    lat, (o,) = run_both(elbm, wl.params, wl.boxes, "f32", 100, "efield 64x64x128 f32", launch=(0, 4, 2),
+    lat, (o,) = run_both(elbm, wl.params, wl.boxes, "f32", 100, "efield 64x64x128 f32", launch=(0, 4, 2, 1),
                          guess="series")
     check_fp32(lat, o, wl.params, wl.boxes[0], 100)
 
