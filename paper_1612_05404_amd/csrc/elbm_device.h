@@ -92,7 +92,9 @@ __host__ __device__ constexpr int tile_dim(int shape, int axis) {
 // k_alpha, which keeps two long FP64-bound waves on every SIMD. With prio set
 // their waves get a higher instruction-issue priority, so that the short,
 // latency-bound sweeps issue first (worth it where that branch is the longer
-// one); it changes no result.
+// one); it changes no result. Called after a kernel's uniform loads: the
+// compiler treats the priority instruction as a side effect and turns the
+// scalar (uniform) loads that follow it into vector loads.
 __device__ __forceinline__ void poisson_branch_priority(int prio) {
   if (prio) __builtin_amdgcn_s_setprio(3);
 }

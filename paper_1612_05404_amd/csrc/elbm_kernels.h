@@ -224,9 +224,9 @@ __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
 // trip less); faces leaving the box are skipped.
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
-  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
+  poisson_branch_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   if (((nd.x + nd.y + nd.z) & 1) != colour) return;
   const uint8_t tt = a.type[nd.g];
@@ -258,17 +258,17 @@ __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
 // Zero-mean gauge of the potential for boxes without Dirichlet nodes.
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
-  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
+  poisson_branch_priority(a.prio);  // after the uniform loads of decode
   double acc[1] = {nd.live ? double(a.phi[nd.g]) : 0.0};
   block_sum_store<1>(acc, a.partials + (int64_t)nd.blk * 4);
 }
 
 __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const double *partials,
                                                   double *scal, int prio) {
-  poisson_branch_priority(prio);
   const BoxDev B = boxes[blockIdx.x];
+  poisson_branch_priority(prio);  // after the uniform box load
   double acc[1] = {0.0};
   for (int i = threadIdx.x; i < B.nblocks; i += BLK) acc[0] += partials[(int64_t)(B.first_block + i) * 4];
   __shared__ double tot[1];
@@ -279,9 +279,9 @@ __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const dou
 
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
-  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
+  poisson_branch_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live || nd.B.has_dirichlet) return;
   a.phi[nd.g] -= F(a.scal[(int64_t)nd.bb * NSCAL + 3]);
 }
@@ -290,9 +290,9 @@ __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
 // takes the centre value, wall nodes carry their fixed potential).
 template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
-  poisson_branch_priority(a.prio);
   Node nd;
   decode(a, nd);
+  poisson_branch_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   const F c = a.phi[nd.g];
   F g0 = F(0), g1 = F(0), g2 = F(0);
