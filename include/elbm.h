@@ -252,14 +252,16 @@ elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dT
  * xcd_remap: 1 orders the node blocks so that each of the 8 XCDs runs one
  * contiguous range of tiles (neighbouring tiles share an L2); 0 keeps the
  * hardware's round-robin order.  graph_steps: steps captured in one HIP graph
- * (even, 2..64).  tile: the collision's block tile, 0 = 256 consecutive nodes
+ * (even, 2..64).  tile: the block tile of the alpha kernel (the first half
+ * of the collision), 0 = 256 consecutive nodes
  * (a 64-thread wave is a run along x), 1 = 8x8x4 nodes (waves 8x8x1),
  * 2 = 8x4x8 (waves 8x4x2), 3 = 4x4x16 (waves 4x4x4): 3-D waves gather the
  * nodes whose alpha needs many Newton updates (at interfaces) into fewer
  * waves.  sweep_priority: 1 raises the instruction-issue priority of the
- * waves of the Poisson branch (SOR sweeps, gauge, E field), which runs beside
- * the alpha kernel on the second stream: it helps when that branch is the
- * longer of the two, 0 (hardware default) when alpha is.  None changes any
+ * waves of the Poisson branch (SOR sweeps, gauge, E field), which runs on the
+ * bound stream while the alpha kernel runs on the library's second stream:
+ * it helps when that branch is the longer of the two, 0 (hardware default)
+ * when alpha is.  None changes any
  * result: per-node arithmetic and the order of every reduction are the same
  * under all mappings. */
 typedef struct elbm_launch {
