@@ -199,8 +199,8 @@ enum {
  * stream around each phase of each following step (a small overhead between
  * launches); enable == 0 stops and discards.  Host-side events only, no device
  * memory.  Without timing the alpha phase runs on a second stream of the
- * library, beside the Poisson and E-field phases; with timing every phase
- * runs in order on the bound stream. */
+ * library, beside the charge, Poisson and E-field phases; with timing every
+ * phase runs in order on the bound stream. */
 elbm_status elbm_set_timing(elbm_ctx *ctx, int32_t enable);
 
 /* Waits for the stream and returns the accumulated device milliseconds per
@@ -258,10 +258,10 @@ elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dT
  * 2 = 8x4x8 (waves 8x4x2), 3 = 4x4x16 (waves 4x4x4): 3-D waves gather the
  * nodes whose alpha needs many Newton updates (at interfaces) into fewer
  * waves.  sweep_priority: 1 raises the instruction-issue priority of the
- * waves of the Poisson branch (SOR sweeps, gauge, E field), which runs on the
- * bound stream while the alpha kernel runs on the library's second stream:
- * it helps when that branch is the longer of the two, 0 (hardware default)
- * when alpha is.  None changes any
+ * waves of the field chain after the densities (gradient, interface, charge,
+ * SOR sweeps, gauge, E field), which runs on the bound stream while the alpha
+ * kernel runs on the library's second stream: it helps when that chain is
+ * the longer of the two branches, 0 (hardware default) when alpha is.  None changes any
  * result: per-node arithmetic and the order of every reduction are the same
  * under all mappings. */
 typedef struct elbm_launch {

@@ -66,7 +66,7 @@ struct elbm_ctx {
   // block tile shape of the collision (0: linear)
   int remap = 0;
   int graph_steps = 2;
-  int prio = 0;  // issue priority of the Poisson-branch waves (0/1)
+  int prio = 0;  // issue priority of the field-chain waves beside k_alpha (0/1)
   int tile = 0;
   // per tile shape: tile -> box table, per-box tile counts, tiles in all
   std::vector<int32_t> tile_box[NTILE_SHAPES];
@@ -238,21 +238,16 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     c->ev_used += per;
   }
   // k_alpha needs only the populations: without phase timing it runs on the
-  // second stream beside the Poisson sweeps and the E field (forked there:
-  // beside the whole chain it slows the density and charge kernels more than
-  // it gains), and k_collide waits for it; with timing everything runs in
-  // order on the bound stream.
+  // second stream beside the rest of the field chain (gradient, interface,
+  // charge, Poisson sweeps, E field), forked after the densities (beside the
+  // density kernel too, the two pulls compete for HBM), and k_collide waits
+  // for it; with timing everything runs in order on the bound stream.
   const dim3 cgrid(c->tile ? (unsigned)c->ntiles[c->tile] : grid.x);
   const bool fork = !c->timing;
   hipStream_t as = fork ? c->aux : c->stream;
   mark(c, ev, 0);
   hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
   mark(c, ev, 1);
-  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
-  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
-  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M);
-  hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
-  mark(c, ev, 2);
   if (fork) {
     HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
@@ -262,6 +257,11 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
       hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
     HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   }
+  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
+  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M, a.prio);
+  hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
+  mark(c, ev, 2);
   for (int sw = 0; sw < c->P.sor_sweeps; ++sw) {
     hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0);
     hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1);
@@ -704,7 +704,7 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
   elbm_launch cur{0, 2, 0, 0};
   elbm_status st = ELBM_OK;
   // four passes, each fixing one knob with the winners of the earlier ones:
-  // tile shape (4), XCD order (2), Poisson-branch priority (2), graph length
+  // tile shape (4), XCD order (2), field-chain priority (2), graph length
   // (3; last, so that every earlier trial captures 2 steps); within a pass two
   // rounds, forward then reverse order, and a candidate's time is the mean of
   // its two: a state that drifts linearly during the trials (an initial

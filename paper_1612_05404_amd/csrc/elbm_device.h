@@ -71,7 +71,7 @@ struct Ptrs {
   int64_t N;            // arena nodes (plane stride)
   int32_t nblocks;      // node blocks of one launch
   int32_t remap;        // 1: XCD-aware block order
-  int32_t prio;         // 1: Poisson-branch waves at raised issue priority
+  int32_t prio;         // 1: field-chain waves beside k_alpha at raised issue priority
   // block tiles of the collision (tx = 0: 256 consecutive nodes per block)
   const int32_t *tile_box;  // [ntiles] box of each tile
   const int4 *box_tiles;    // [nboxes] first tile, tiles along x, y, z
@@ -88,14 +88,15 @@ __host__ __device__ constexpr int tile_dim(int shape, int axis) {
        : shape == 3 ? (axis == 0 ? 4 : axis == 1 ? 4 : 16) : 0;
 }
 
-// Kernels of the Poisson branch (SOR sweeps, gauge, E field) run beside
-// k_alpha, which keeps two long FP64-bound waves on every SIMD. With prio set
-// their waves get a higher instruction-issue priority, so that the short,
-// latency-bound sweeps issue first (worth it where that branch is the longer
-// one); it changes no result. Called after a kernel's uniform loads: the
-// compiler treats the priority instruction as a side effect and turns the
-// scalar (uniform) loads that follow it into vector loads.
-__device__ __forceinline__ void poisson_branch_priority(int prio) {
+// The field-chain kernels after the densities (gradient, interface, charge,
+// SOR sweeps, gauge, E field) run beside k_alpha, which keeps two long
+// FP64-bound waves on every SIMD. With prio set their waves get a higher
+// instruction-issue priority, so that these short, latency-bound kernels
+// issue first (worth it where the chain is the longer branch); it changes no
+// result. Called after a kernel's uniform loads: the compiler treats the
+// priority instruction as a side effect and turns the scalar (uniform) loads
+// that follow it into vector loads.
+__device__ __forceinline__ void field_chain_priority(int prio) {
   if (prio) __builtin_amdgcn_s_setprio(3);
 }
 

@@ -12,7 +12,7 @@
 //   k_sor x 2k     red-black SOR half sweeps
 //   (gauge)        zero-mean potential for boxes without Dirichlet nodes
 //   k_efield       |E|^2 with E = E_ext - grad phi
-//   k_alpha        (second stream, beside the kernels above) pull, FP64 alpha
+//   k_alpha        (second stream, beside the kernels from k_gradient on) pull, FP64 alpha
 //                  Newton, Carreau beta -> alpha * beta
 //   k_collide      pull again, Shan-Chen + electric force, exact-difference
 //                  source, write f*
@@ -85,6 +85,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   F g0 = F(0), g1 = F(0), g2 = F(0);
   if ((a.type[nd.g] & 3) != K_SOLID) {
@@ -122,6 +123,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
   Node nd;
   decode(a, nd);
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (nd.live) {
     const uint8_t tt = a.type[nd.g];
@@ -168,8 +170,9 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
 // partials; then the charge scales (conserving: Q/integral, generator: xi)
 // and the neutralising background qbar = sum_unknown q / N_unknown.
 __global__ __launch_bounds__(BLK) void k_charge_coef(const BoxDev *boxes, const double *partials,
-                                                     double *scal, Model M) {
+                                                     double *scal, Model M, int prio) {
   const BoxDev B = boxes[blockIdx.x];
+  field_chain_priority(prio);  // after the uniform box load
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < B.nblocks; i += BLK)
 #pragma unroll
@@ -201,6 +204,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   const double *sc = a.scal + (int64_t)nd.bb * NSCAL;
   const uint8_t tt = a.type[nd.g];
@@ -226,7 +230,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
   Node nd;
   decode(a, nd);
-  poisson_branch_priority(a.prio);  // after the uniform loads of decode
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   if (((nd.x + nd.y + nd.z) & 1) != colour) return;
   const uint8_t tt = a.type[nd.g];
@@ -260,7 +264,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
-  poisson_branch_priority(a.prio);  // after the uniform loads of decode
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   double acc[1] = {nd.live ? double(a.phi[nd.g]) : 0.0};
   block_sum_store<1>(acc, a.partials + (int64_t)nd.blk * 4);
 }
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(BLK) void k_phi_partials(Ptrs<T, F> a) {
 __global__ __launch_bounds__(BLK) void k_phi_mean(const BoxDev *boxes, const double *partials,
                                                   double *scal, int prio) {
   const BoxDev B = boxes[blockIdx.x];
-  poisson_branch_priority(prio);  // after the uniform box load
+  field_chain_priority(prio);  // after the uniform box load
   double acc[1] = {0.0};
   for (int i = threadIdx.x; i < B.nblocks; i += BLK) acc[0] += partials[(int64_t)(B.first_block + i) * 4];
   __shared__ double tot[1];
@@ -281,7 +285,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
-  poisson_branch_priority(a.prio);  // after the uniform loads of decode
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live || nd.B.has_dirichlet) return;
   a.phi[nd.g] -= F(a.scal[(int64_t)nd.bb * NSCAL + 3]);
 }
@@ -292,7 +296,7 @@ template <typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
-  poisson_branch_priority(a.prio);  // after the uniform loads of decode
+  field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
   const F c = a.phi[nd.g];
   F g0 = F(0), g1 = F(0), g2 = F(0);

@@ -394,7 +394,7 @@ class Lattice:
 
     def autotune(self, steps_per_trial: int = 32):
         """Chooses the launch mapping in four timed passes (collision tile
-        0..3, then XCD order 0, 1, then Poisson-branch priority 0, 1, then
+        0..3, then XCD order 0, 1, then field-chain priority 0, 1, then
         graph length 2, 4, 8); returns it and each candidate's ms per step in
         that order.  The trial steps advance the state like ordinary steps
         (22 trials + 60 in all)."""
