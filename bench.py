@@ -43,8 +43,8 @@ ROOF_AT, ROOF_STEPS = 250, 16  # the roofline window: steps 251..266
 # WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives for the same
 # counters).  None: not counted for the current kernels.
 ALPHA_FP64_FLOP_PER_NODE = 10954
-ALPHA_TRAFFIC_BYTES = 377_668_508
-COLLIDE_TRAFFIC_BYTES = 216_242_037
+ALPHA_TRAFFIC_BYTES = 377_100_296
+COLLIDE_TRAFFIC_BYTES = 216_229_999
 
 
 def alpha_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
