@@ -179,7 +179,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000,
                     help="timed steps (default: the field drop's configured run length)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32"])
+    ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32", "ensemble"],
+                    help="ensemble only with --roofline-only (the default run times it in its own leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--alpha-guess", default="series", choices=["series", "standard", "mlp"],
                     help="initial guess of the alpha Newton iteration for the reported value")
@@ -195,6 +196,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the collision's roofline window (for counter runs)")
     args = ap.parse_args()
+    if args.workload == "ensemble" and not args.roofline_only:
+        ap.error("--workload ensemble serves --roofline-only counter runs; the default run times the ensemble itself")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
