@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--jet-warmup", type=int, default=200)
     ap.add_argument("--jet-steps", type=int, default=100)
     ap.add_argument("--launch", default=None,
-                    help="launch mapping remap,graph_steps,tile,sweep_priority (skips the autotuner)")
+                    help="launch mapping remap,graph_steps,tile[,sweep_priority] (skips the autotuner)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the collision's roofline window (for counter runs)")
     args = ap.parse_args()
@@ -235,8 +235,10 @@ def main():
 
     def tuned_launch(mode):
         if args.launch:
-            r, g, t, p = (int(v) for v in args.launch.split(","))
-            return {"xcd_remap": r, "graph_steps": g, "tile": t, "sweep_priority": p}
+            v = [int(x) for x in args.launch.split(",")]
+            if len(v) not in (3, 4):
+                sys.exit(f"--launch takes remap,graph_steps,tile[,sweep_priority], got {args.launch!r}")
+            return {"xcd_remap": v[0], "graph_steps": v[1], "tile": v[2], "sweep_priority": v[3] if len(v) == 4 else 0}
         # tuned on a throw-away instance: the timed runs start from the initial state
         lat = make(mode)
         lat.step(args.warmup, record=False)
