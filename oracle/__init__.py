@@ -46,6 +46,7 @@ class OraParams(ct.Structure):
         ("E_ext", ct.c_double * 3),
         ("sor_omega", ct.c_double), ("newton_rtol", ct.c_double),
         ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
+        ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("pad2_", ct.c_int32),
     ]
 
 
@@ -84,6 +85,16 @@ def lib():
         L.ora_threads.restype = ct.c_int
         L.ora_poisson.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                   ct.c_double]
+        L.ora_poisson_rhs.restype = ct.c_double
+        L.ora_poisson_rhs.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.ora_poisson_residual.restype = ct.c_double
+        L.ora_poisson_residual.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                           ct.POINTER(ct.c_double)]
+        L.ora_poisson_solve.restype = ct.c_int
+        L.ora_poisson_solve.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
+                                        ct.c_double, ct.c_double, ct.c_int, ct.POINTER(ct.c_double),
+                                        ct.POINTER(ct.c_double)]
+        L.ora_poisson_stats.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
         _lib = L
     return _lib
 
@@ -153,6 +164,8 @@ def make_params(p, box, nthreads: int = 0) -> OraParams:
         P.E_ext[a] = float(E[a])
     P.sor_omega = float(info.get("sor_omega", p.sor_omega))
     P.newton_rtol = p.newton_rtol
+    P.sor_tol = float(getattr(p, "sor_tol", 0.0))
+    P.sor_check_every = int(getattr(p, "sor_check_every", 0))
     for s in range(2):
         P.rho_in[s] = p.rho_in[s]
         P.rho_out[s] = p.rho_out[s]
@@ -218,6 +231,42 @@ class Oracle:
     def set_phi(self, phi: np.ndarray):
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         lib().ora_set_phi(self.h, phi.ctypes.data)
+
+    def poisson_stats(self):
+        """Residual, its scale max|rhs|, sweeps done of the last step's Poisson
+        solve, and the number of steps whose solve missed the tolerance."""
+        d = np.zeros(2)
+        i = np.zeros(2, dtype=np.int64)
+        lib().ora_poisson_stats(self.h, d.ctypes.data, i.ctypes.data)
+        return dict(residual=float(d[0]), scale=float(d[1]), sweeps=int(i[0]), noconv=int(i[1]))
+
+    def poisson_rhs(self, eps, q):
+        """The step's Poisson right-hand side for given eps and q: (rhs, qbar)."""
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        rhs = np.zeros(self.shape)
+        qbar = lib().ora_poisson_rhs(self.h, eps.ctypes.data, q.ctypes.data, rhs.ctypes.data)
+        return rhs, qbar
+
+    def poisson_residual(self, eps, rhs, phi):
+        """(max residual over unknown nodes, max|rhs| over the same nodes)."""
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        sc = ct.c_double()
+        r = lib().ora_poisson_residual(self.h, eps.ctypes.data, rhs.ctypes.data, phi.ctypes.data, ct.byref(sc))
+        return r, sc.value
+
+    def poisson_solve(self, eps, rhs, phi, sweeps, omega, tol=0.0, check_every=0):
+        """The step's stopping SOR on given eps/rhs, phi updated in place:
+        (sweeps done, residual, scale)."""
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        assert phi.flags.c_contiguous and phi.dtype == np.float64
+        r, sc = ct.c_double(), ct.c_double()
+        n = lib().ora_poisson_solve(self.h, eps.ctypes.data, rhs.ctypes.data, phi.ctypes.data, int(sweeps),
+                                    float(omega), float(tol), int(check_every), ct.byref(r), ct.byref(sc))
+        return n, r.value, sc.value
 
     def poisson(self, eps, rhs, phi, sweeps, omega):
         """Run the oracle's red-black SOR on given eps/rhs, updating phi in place."""

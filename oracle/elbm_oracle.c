@@ -70,6 +70,11 @@ typedef struct {
     double E_ext[3];
     double sor_omega, newton_rtol;
     double rho_in[2], rho_out[2];
+    /* Poisson stop rule: sor_tol > 0 ends the sweeps once the residual is at
+     * most sor_tol * max|rhs| (checked after every sor_check_every sweeps when
+     * that is > 0, and after the last one); sor_tol = 0: exactly sor_sweeps */
+    double sor_tol;
+    int32_t sor_check_every, pad2_;
 } ora_params;
 
 typedef struct {
@@ -106,6 +111,12 @@ typedef struct {
     int64_t nerr_nonfinite, nerr_negative;
     int has_dirichlet;
     int64_t n_unknown;
+    /* Poisson solve of the last step: residual max|sum_f eps_f (phi_nb - phi)
+     * - rhs| over the unknown nodes after the last sweep, its scale max|rhs|,
+     * sweeps done; steps whose solve missed the tolerance */
+    double sor_res, sor_scale;
+    int32_t sor_done;
+    int64_t sor_noconv;
 } ora_state;
 
 /* ---------------------------------------------------------------- sums */
@@ -549,30 +560,25 @@ static void charge(ora_state *s) {
 
 static const int FACE[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
-/* Red-black SOR for div(eps grad phi) = div(eps E_ext) - (q - qbar)
- * (Gauss law, Sec. II; eps = 1 + rho_A, faces carry the mean of the two
- * node permittivities).  A uniform neutralising charge qbar makes the net
- * charge zero; Dirichlet nodes keep their potential; a face that leaves the
- * domain carries no flux.  A box without Dirichlet nodes is gauged to zero
- * mean potential after the sweeps. */
-void ora_poisson(const ora_state *s_, const double *eps, const double *rhs, double *phi,
-                 int sweeps, double omega);
-
-static void poisson(ora_state *s) {
-    const int64_t N = s->N;
-    const double *rA = s->rho;
+/* Right-hand side of the discrete Gauss law (Sec. II: div(eps E) = q with
+ * E = E_ext - grad phi, eps = 1 + rho_A), written per node as
+ *   sum_f eps_f (phi_nb - phi) = sum_f eps_f E_ext . e_f - (q - qbar),
+ * the sums over the six faces f that stay in the domain, eps_f the mean of
+ * the two node permittivities, e_f the face's unit vector.  The first sum
+ * is the outward flux of eps E_ext through the node's faces; qbar is the
+ * uniform neutralising charge, the mean of q over the Poisson-unknown
+ * nodes.  Returns qbar. */
+double ora_poisson_rhs(const ora_state *s, const double *eps, const double *q, double *rhs) {
     nsum qs = {0, 0};
-    for (int64_t n = 0; n < N; ++n)
-        if (!(s->type[n] & T_DIRICHLET)) ns_add(&qs, s->q[n]);
-    s->qbar = s->n_unknown ? ns_val(&qs) / (double)s->n_unknown : 0.0;
-    double *eps = (double *)malloc(N * sizeof(double));
-    for (int64_t n = 0; n < N; ++n) eps[n] = 1.0 + rA[n];
+    for (int64_t n = 0; n < s->N; ++n)
+        if (!(s->type[n] & T_DIRICHLET)) ns_add(&qs, q[n]);
+    const double qbar = s->n_unknown ? ns_val(&qs) / (double)s->n_unknown : 0.0;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < s->P.nz; ++z)
         for (int y = 0; y < s->P.ny; ++y)
             for (int x = 0; x < s->P.nx; ++x) {
                 int64_t n = node_index(s, x, y, z);
-                double r = -(s->q[n] - s->qbar);
+                double r = -(q[n] - qbar);
                 for (int f = 0; f < 6; ++f) {
                     int64_t m = neighbour(s, x, y, z, FACE[f][0], FACE[f][1], FACE[f][2]);
                     if (m < 0) continue;
@@ -580,41 +586,116 @@ static void poisson(ora_state *s) {
                     r += ef * (s->P.E_ext[0] * FACE[f][0] + s->P.E_ext[1] * FACE[f][1] +
                                s->P.E_ext[2] * FACE[f][2]);
                 }
-                s->rhs[n] = r;
+                rhs[n] = r;
             }
-    ora_poisson(s, eps, s->rhs, s->phi, s->P.sor_sweeps, s->P.sor_omega);
-    free(eps);
+    return qbar;
 }
 
+/* Largest residual |sum_f eps_f (phi_nb - phi) - rhs| over the unknown
+ * nodes; *scale (may be NULL) receives max|rhs| over the same nodes. */
+double ora_poisson_residual(const ora_state *s, const double *eps, const double *rhs,
+                            const double *phi, double *scale) {
+    double rmax = 0.0, smax = 0.0;
+    for (int z = 0; z < s->P.nz; ++z)
+        for (int y = 0; y < s->P.ny; ++y)
+            for (int x = 0; x < s->P.nx; ++x) {
+                int64_t n = node_index(s, x, y, z);
+                if (s->type[n] & T_DIRICHLET) continue;
+                double acc = 0.0;
+                for (int f = 0; f < 6; ++f) {
+                    int64_t m = neighbour(s, x, y, z, FACE[f][0], FACE[f][1], FACE[f][2]);
+                    if (m < 0) continue;
+                    acc += 0.5 * (eps[n] + eps[m]) * (phi[m] - phi[n]);
+                }
+                double r = fabs(acc - rhs[n]);
+                if (r > rmax) rmax = r;
+                if (fabs(rhs[n]) > smax) smax = fabs(rhs[n]);
+            }
+    if (scale) *scale = smax;
+    return rmax;
+}
+
+/* One red-black SOR sweep (Sec. II: SOR for the Poisson equation): red
+ * nodes ((x + y + z) even) first, each set to the over-relaxed solution of
+ * its own equation; Dirichlet nodes keep their potential. */
+static void sor_sweep(const ora_state *s, const double *eps, const double *rhs, double *phi,
+                      double omega) {
+    for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < s->P.nz; ++z)
+            for (int y = 0; y < s->P.ny; ++y)
+                for (int x = 0; x < s->P.nx; ++x) {
+                    if (((x + y + z) & 1) != colour) continue;
+                    int64_t n = node_index(s, x, y, z);
+                    if (s->type[n] & T_DIRICHLET) continue;
+                    double A = 0.0, B = 0.0;
+                    for (int f = 0; f < 6; ++f) {
+                        int64_t m = neighbour(s, x, y, z, FACE[f][0], FACE[f][1], FACE[f][2]);
+                        if (m < 0) continue;
+                        double ef = 0.5 * (eps[n] + eps[m]);
+                        A += ef;
+                        B += ef * phi[m];
+                    }
+                    phi[n] = (1.0 - omega) * phi[n] + omega * (B - rhs[n]) / A;
+                }
+    }
+}
+
+/* Zero-mean gauge of a domain without Dirichlet nodes (the periodic problem
+ * fixes phi only up to a constant). */
+static void gauge(const ora_state *s, double *phi) {
+    if (s->has_dirichlet) return;
+    nsum m = {0, 0};
+    for (int64_t n = 0; n < s->N; ++n) ns_add(&m, phi[n]);
+    double mean = ns_val(&m) / (double)s->N;
+    for (int64_t n = 0; n < s->N; ++n) phi[n] -= mean;
+}
+
+/* Red-black SOR with a stop rule: at most `sweeps` sweeps; with tol > 0 the
+ * residual is checked after every `check_every` sweeps (0: only after the
+ * last) and the sweeps end once it is at most tol * max|rhs|.  The residual
+ * after the last sweep done goes to *res, max|rhs| to *scale, the sweeps
+ * done are returned; then the gauge.  Residuals are taken before the gauge
+ * (they do not depend on it). */
+int ora_poisson_solve(const ora_state *s, const double *eps, const double *rhs, double *phi,
+                      int sweeps, double omega, double tol, int check_every, double *res,
+                      double *scale) {
+    int done = 0;
+    double r = 0.0, sc = 0.0;
+    int have = 0;
+    while (done < sweeps) {
+        sor_sweep(s, eps, rhs, phi, omega);
+        ++done;
+        have = 0;
+        if (tol > 0.0 && check_every > 0 && done % check_every == 0 && done < sweeps) {
+            r = ora_poisson_residual(s, eps, rhs, phi, &sc);
+            have = 1;
+            if (r <= tol * sc) break;
+        }
+    }
+    if (!have) r = ora_poisson_residual(s, eps, rhs, phi, &sc);
+    gauge(s, phi);
+    if (res) *res = r;
+    if (scale) *scale = sc;
+    return done;
+}
+
+/* Exactly `sweeps` sweeps (then the gauge), for the solver pins. */
 void ora_poisson(const ora_state *s, const double *eps, const double *rhs, double *phi,
                  int sweeps, double omega) {
+    for (int sw = 0; sw < sweeps; ++sw) sor_sweep(s, eps, rhs, phi, omega);
+    gauge(s, phi);
+}
+
+static void poisson(ora_state *s) {
     const int64_t N = s->N;
-    for (int sw = 0; sw < sweeps; ++sw)
-        for (int colour = 0; colour < 2; ++colour) {
-#pragma omp parallel for schedule(static)
-            for (int z = 0; z < s->P.nz; ++z)
-                for (int y = 0; y < s->P.ny; ++y)
-                    for (int x = 0; x < s->P.nx; ++x) {
-                        if (((x + y + z) & 1) != colour) continue;
-                        int64_t n = node_index(s, x, y, z);
-                        if (s->type[n] & T_DIRICHLET) continue;
-                        double A = 0.0, B = 0.0;
-                        for (int f = 0; f < 6; ++f) {
-                            int64_t m = neighbour(s, x, y, z, FACE[f][0], FACE[f][1], FACE[f][2]);
-                            if (m < 0) continue;
-                            double ef = 0.5 * (eps[n] + eps[m]);
-                            A += ef;
-                            B += ef * phi[m];
-                        }
-                        phi[n] = (1.0 - omega) * phi[n] + omega * (B - rhs[n]) / A;
-                    }
-        }
-    if (!s->has_dirichlet) {
-        nsum m = {0, 0};
-        for (int64_t n = 0; n < N; ++n) ns_add(&m, phi[n]);
-        double mean = ns_val(&m) / (double)N;
-        for (int64_t n = 0; n < N; ++n) phi[n] -= mean;
-    }
+    double *eps = (double *)malloc(N * sizeof(double));
+    for (int64_t n = 0; n < N; ++n) eps[n] = 1.0 + s->rho[n];
+    s->qbar = ora_poisson_rhs(s, eps, s->q, s->rhs);
+    s->sor_done = ora_poisson_solve(s, eps, s->rhs, s->phi, s->P.sor_sweeps, s->P.sor_omega,
+                                    s->P.sor_tol, s->P.sor_check_every, &s->sor_res, &s->sor_scale);
+    if (s->P.sor_tol > 0.0 && !(s->sor_res <= s->P.sor_tol * s->sor_scale)) s->sor_noconv++;
+    free(eps);
 }
 
 /* E = E_ext - grad phi (19-point gradient), |E|^2, and the electric body
@@ -867,6 +948,13 @@ void ora_set_phi(ora_state *s, const double *phi) { memcpy(s->phi, phi, s->N * s
 void ora_counters(const ora_state *s, int64_t out_i[3], double out_d[3]) {
     out_i[0] = s->nfallback; out_i[1] = s->nerr_nonfinite; out_i[2] = s->nerr_negative;
     out_d[0] = s->Sb; out_d[1] = s->Ss; out_d[2] = s->qbar;
+}
+
+/* Poisson solve of the last step: residual and its scale max|rhs|, sweeps
+ * done, and the steps whose solve missed the tolerance so far. */
+void ora_poisson_stats(const ora_state *s, double out_d[2], int64_t out_i[2]) {
+    out_d[0] = s->sor_res; out_d[1] = s->sor_scale;
+    out_i[0] = s->sor_done; out_i[1] = s->sor_noconv;
 }
 
 /* Lattice tables (for the tests). */

@@ -76,9 +76,13 @@ class Params:
     rho_th: float = 0.5
     w_theta: float = 0.05
     E_ext: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])
-    # Poisson: red-black SOR, fixed sweep count per step
+    # Poisson: red-black SOR, at most sor_sweeps sweeps per step; sor_tol > 0
+    # stops them once the residual is at most sor_tol * max|rhs| (checked after
+    # every sor_check_every sweeps, 0 = after the last only)
     sor_omega: float = 1.6
     sor_sweeps: int = 8
+    sor_tol: float = 0.0
+    sor_check_every: int = 0
     # entropic alpha Newton
     newton_rtol: float = 1e-12
     newton_max: int = 30
