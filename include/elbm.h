@@ -42,8 +42,10 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 3u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
-                                 3: sweep_priority in elbm_launch */
+#define ELBM_ABI_VERSION 4u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
+                                 3: sweep_priority in elbm_launch;
+                                 4: Poisson stop rule and residual, strict error flags, Halley
+                                    iteration, electric force and solver fields in elbm_diag */
 
 typedef struct elbm_ctx elbm_ctx;
 
@@ -53,8 +55,18 @@ typedef enum {
     ELBM_ENOMEM = -2,      /* arena too small or host allocation failed     */
     ELBM_EHIP = -3,        /* a HIP runtime call failed                     */
     ELBM_ENONFINITE = -4,  /* a post-collision population became non-finite */
+    ELBM_ENEGPOP = -5,     /* a post-collision population became negative
+                              (only with ELBM_STRICT_NEGPOP)                */
+    ELBM_ENOCONV = -6,     /* a Poisson solve ended above its tolerance, or
+                              (with ELBM_STRICT_ALPHA) an alpha solve fell
+                              back                                          */
     ELBM_ESTATE = -7       /* call out of order (e.g. step before bind)     */
 } elbm_status;
+
+/* elbm_params.strict: device conditions that, besides non-finite
+ * populations (always), set the sticky error word that elbm_sync reports.
+ * Without them the conditions are only counted (elbm_diag). */
+enum { ELBM_STRICT_NEGPOP = 1, ELBM_STRICT_ALPHA = 2 };
 
 /* Storage: F64 = FP64 populations and fields; F32 = FP32 populations with
  * FP64 auxiliary fields (densities, psi, charge, potential, |E|^2);
@@ -62,13 +74,17 @@ typedef enum {
  * are FP64 in every mode. */
 enum { ELBM_STORAGE_F64 = 0, ELBM_STORAGE_F32 = 1, ELBM_STORAGE_F32_ALL = 2 };
 enum { ELBM_CHARGE_CONSERVING = 0, ELBM_CHARGE_GENERATOR = 1 };
-/* Initial guess of the alpha Newton iteration; every guess is polished to the
+/* Initial guess of the alpha iteration; every guess is polished to the
  * same stopping rule.  STANDARD: alpha0 = 2 (the BGK value).  SERIES: root of
- * the degree-7 truncation of the entropy balance in powers of alpha (no
+ * the degree-11 truncation of the entropy balance in powers of alpha (no
  * logarithms), used inside the positivity interval while alpha0 max|x| < 1.2.
  * MLP: the series starter where it is used, the learned starter elsewhere
  * (see elbm_mlp_* below). */
 enum { ELBM_GUESS_STANDARD = 0, ELBM_GUESS_MLP = 1, ELBM_GUESS_SERIES = 2 };
+/* The iteration itself: NEWTON on the entropy balance g(alpha) = H(f +
+ * alpha Delta) - H(f) (Eqs. entropic, H), or HALLEY, which also uses
+ * g'' = sum_p Delta_p x_p / (1 + alpha x_p) (no further logarithm). */
+enum { ELBM_ITER_NEWTON = 0, ELBM_ITER_HALLEY = 1 };
 
 /* Model constants shared by every box of a context. */
 typedef struct {
@@ -81,7 +97,7 @@ typedef struct {
     int32_t sor_sweeps;       /* red-black SOR sweeps per step (>= 0)               */
     int32_t newton_max;       /* max Newton updates for alpha (>= 1)                */
     int32_t alpha_guess;      /* ELBM_GUESS_*                                       */
-    int32_t pad_;
+    int32_t strict;           /* ELBM_STRICT_* mask (0: only non-finite is an error) */
     double G[2][2];           /* Shan-Chen couplings G[s][s'] (Eq. sc)              */
     double Gw[2][2];          /* fluid-wall couplings Gw[s][s'] (Eq. sc, wall sum): a wall
                                  neighbour carries the node's own psi^s'; Gw = G is a
@@ -94,6 +110,14 @@ typedef struct {
     double rho_in[2];         /* inlet densities at start, and for an inlet node
                                  without fluid neighbours                           */
     double rho_out[2];        /* component densities held at outlet nodes           */
+    double sor_tol;           /* > 0: Poisson sweeps stop once the residual
+                                 max|sum_f eps_f (phi_nb - phi) - rhs| is at most
+                                 sor_tol * max|rhs| (unknown nodes of the box, FP64),
+                                 and a solve that ends above it sets ELBM_ENOCONV;
+                                 0: exactly sor_sweeps sweeps                      */
+    int32_t sor_check_every;  /* with sor_tol > 0: residual checked after every so
+                                 many sweeps (0: after the last only)              */
+    int32_t alpha_iter;       /* ELBM_ITER_*                                        */
 } elbm_params;
 
 /* One lattice box.  Boxes of one context are independent (no exchange). */
@@ -106,26 +130,42 @@ typedef struct {
     double sor_omega;         /* SOR over-relaxation factor in (0, 2)               */
 } elbm_box;
 
-/* Diagnostics of one box, read from the current state. */
+/* Diagnostics of one box (conservation checks of Sec. II.C: mass per
+ * component, momentum, the electric body force; solver statistics). */
 typedef struct {
     double mass[2];           /* sum over nodes of sum_p f, per component           */
     double momentum[3];       /* sum over nodes, components and p of c_p f          */
-    double alpha_min, alpha_max, alpha_mean;  /* over fluid nodes, last recorded step */
-    double mean_newton_iters; /* Newton updates per (node, component), all steps    */
+    double alpha_min, alpha_max, alpha_mean;  /* over fluid (node, component) pairs,
+                                 last recorded step (device reduction)             */
+    double mean_newton_iters; /* alpha updates per (node, component), all steps     */
     int64_t n_fallback;       /* alpha fallbacks (no root / no convergence), all steps */
     int64_t n_negative;       /* negative post-collision populations, all steps     */
     int64_t n_collisions;     /* (node, component) collisions counted, all steps    */
+    double sum_Fel[3];        /* sum over fluid nodes of the electric force Eq.
+                                 force_el2, last recorded step: with periodic walls
+                                 the step changes the momentum by exactly this     */
+    double sor_residual;      /* Poisson residual after the last sweep of the last
+                                 step that took it (recorded steps, and every step
+                                 with sor_tol > 0)                                 */
+    double sor_scale;         /* max|rhs| of that solve                             */
+    int32_t sor_sweeps;       /* sweeps that solve ran                              */
+    int32_t pad_;
+    int64_t n_sor_noconv;     /* solves that ended above sor_tol, all steps        */
 } elbm_diag;
 
 /* ABI version of the loaded library (ELBM_ABI_VERSION). */
 uint32_t elbm_abi_version(void);
 
 /* Validates params and boxes (copied), lays out the arena.  *out owns host
- * memory only; release it with elbm_destroy. */
+ * memory only; release it with elbm_destroy.  The model constants are those
+ * of Sec. II (Shan-Chen couplings of Eq. sc, the Carreau law of Eq. carreau,
+ * the charge models of Eqs. surface-q2 / surface-q3).  EINVAL on a bad value
+ * (nothing is kept). */
 elbm_status elbm_create(const elbm_params *params, const elbm_box *boxes, int32_t nboxes,
                         elbm_ctx **out);
 
-/* Bytes of device memory the context needs in its arena. */
+/* Bytes of device memory the context needs in its arena (all fields of every
+ * box, structure of arrays; see the layout notes in the library source). */
 elbm_status elbm_required_bytes(const elbm_ctx *ctx, size_t *bytes);
 
 /* Binds the caller-owned device arena (256-byte aligned, >= required bytes)
@@ -142,16 +182,23 @@ elbm_status elbm_bind(elbm_ctx *ctx, void *dev_arena, size_t bytes, void *hip_st
  * f_eq(rho_in, u_bc), outlet nodes at f_eq(rho_out, 0), solid nodes at 0.
  * Every step resets an inlet node to f_eq(rho_nb, u_bc) per component, rho_nb
  * the w-weighted mean density of its fluid neighbours (a velocity inlet whose
- * density is that of the liquid next to it, as in the jet set-up of Sec. IV);
+ * density is that of the liquid next to it, as in the jet set-up of Sec. III.B);
  * outlet nodes keep theirs. */
 elbm_status elbm_set_box(elbm_ctx *ctx, int32_t box, const uint8_t *node_type, const double *rho,
                          const double *u, const double *phi, const double *u_bc, const double *xi,
                          double jitter);
 
-/* Enqueues nsteps time steps of every box on the bound stream (asynchronous).
+/* Enqueues nsteps time steps of every box on the bound stream (asynchronous):
+ * each step is the update of Sec. II.C in the order of its summary (stream,
+ * moments, charge of Eq. surface-q2/q3, Poisson solve of the Gauss law,
+ * electric force Eq. force_el2, Shan-Chen force Eq. sc, alpha of Eq.
+ * entropic, Carreau viscosity and beta of Eqs. strain2/carreau/beta,
+ * collision Eq. lattice-b with the source of Eq. add).
  * record != 0: the last step also stores the recorded fields (component
- * densities, half-step velocity, alpha and Newton iterations) that the
- * elbm_read_* calls return. */
+ * densities, half-step velocity of Sec. II, alpha and its updates, the
+ * electric-force sum and the Poisson residual) that the elbm_read_* and
+ * elbm_diagnostics calls return.  Device conditions set the sticky word that
+ * elbm_sync reports; EINVAL for nsteps < 0, ESTATE before bind. */
 elbm_status elbm_step(elbm_ctx *ctx, int32_t nsteps, int32_t record);
 
 /* enable != 0 (the default): elbm_step replays pairs of unrecorded steps as a
@@ -160,28 +207,38 @@ elbm_status elbm_step(elbm_ctx *ctx, int32_t nsteps, int32_t record);
  * every kernel is launched directly.  Results are bitwise identical. */
 elbm_status elbm_set_graphs(elbm_ctx *ctx, int32_t enable);
 
-/* Waits for the stream; returns ELBM_ENONFINITE if any step produced a
- * non-finite population since bind (sticky). */
+/* Waits for the stream and reports the sticky device error word since bind:
+ * ELBM_ENONFINITE (a non-finite post-collision population), else
+ * ELBM_ENEGPOP (a negative one, with ELBM_STRICT_NEGPOP), else ELBM_ENOCONV
+ * (a Poisson solve above sor_tol, or with ELBM_STRICT_ALPHA an alpha
+ * fallback: no root of Eq. entropic in the positivity interval or no
+ * convergence).  elbm_last_error names the condition. */
 elbm_status elbm_sync(elbm_ctx *ctx);
 
 /* Reads (synchronising first) from the last recorded step:
- *  rho [C][N] component densities after streaming, u [3][N] half-step
- *  velocity sum_s (j_s + F_s/2) / sum_s rho_s (Sec. II, after Eq. add). */
+ *  rho [C][N] component densities after streaming (zeroth moment of Eq.
+ *  lattice-b's populations), u [3][N] half-step velocity
+ *  sum_s (j_s + F_s/2) / sum_s rho_s (Sec. II, after Eq. add). */
 elbm_status elbm_read_moments(elbm_ctx *ctx, int32_t box, double *rho, double *u);
-/* potential phi [N] after the last step's Poisson solve */
+/* potential phi [N] after the last step's Poisson solve (Sec. II, Gauss
+ * law div(eps E) = q, E = E_ext - grad phi; Dirichlet nodes hold theirs) */
 elbm_status elbm_read_potential(elbm_ctx *ctx, int32_t box, double *phi);
-/* free charge q [N] of the last step (without the neutralising background) */
+/* free charge q [N] of the last step, Eq. surface-q2 or surface-q3 (without
+ * the neutralising background) */
 elbm_status elbm_read_charge(elbm_ctx *ctx, int32_t box, double *q);
-/* alpha [C][N] and Newton updates iters [C][N] (-1 = fallback) of the last
- * recorded step; zeros at non-fluid nodes.  iters may be NULL. */
+/* alpha [C][N] of Eq. entropic and its updates iters [C][N] (-1 = fallback)
+ * of the last recorded step; zeros at non-fluid nodes.  iters may be NULL. */
 elbm_status elbm_read_alpha(elbm_ctx *ctx, int32_t box, double *alpha, int32_t *iters);
-/* current post-collision populations [C][19][N] (get) / replace them (set) */
+/* current post-collision populations [C][19][N] of Eq. lattice-b (get) /
+ * replace them (set): with elbm_set_potential, a checkpoint of the state */
 elbm_status elbm_get_populations(elbm_ctx *ctx, int32_t box, double *f);
 elbm_status elbm_set_populations(elbm_ctx *ctx, int32_t box, const double *f);
-/* replaces the potential [N] (warm start of the next solve) */
+/* replaces the potential [N] (warm start of the next Poisson solve) */
 elbm_status elbm_set_potential(elbm_ctx *ctx, int32_t box, const double *phi);
 
-/* Conservation and solver diagnostics of one box. */
+/* Conservation and solver diagnostics of one box (elbm_diag above): mass and
+ * momentum of the current populations, alpha statistics and the electric-force
+ * sum of the last recorded step, counters since bind.  Synchronous. */
 elbm_status elbm_diagnostics(elbm_ctx *ctx, int32_t box, elbm_diag *out);
 
 /* Phases of one step for elbm_timing. */
@@ -219,7 +276,8 @@ elbm_status elbm_timing(elbm_ctx *ctx, double *ms, int64_t *steps);
  * Parameters: FP32 vector of 1761 floats, in order W1[32][20], b1[32],
  * W2[32][32], b2[32], w3[32], b3. */
 
-/* Sets the parameters (host, n = 1761) and clears the optimiser state. */
+/* Sets the parameters (host, n = 1761) and clears the optimiser state.  The
+ * network approximates the root of Eqs. entropic / H that Newton polishes. */
 elbm_status elbm_mlp_set_weights(elbm_ctx *ctx, const float *w, int64_t n);
 /* Copies the current parameters to the host (n = 1761). */
 elbm_status elbm_mlp_get_weights(elbm_ctx *ctx, float *w, int64_t n);

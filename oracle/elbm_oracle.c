@@ -779,7 +779,7 @@ static void forces(ora_state *s) {
             }
 }
 
-/* Velocity inlet (the jet set-up of Sec. IV: Poiseuille velocity at the
+/* Velocity inlet (the jet set-up of Sec. III.B: Poiseuille velocity at the
  * inlet nodes, density that of the liquid): after each step's moments an
  * inlet node holds f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted
  * mean density of its fluid neighbours, sum_p w_p rho(r + c_p) / sum_p w_p

@@ -43,7 +43,7 @@ struct elbm_ctx {
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
   size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_nbm, o_reca,
-      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_scal, o_cnt, o_err, total;
+      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
@@ -116,6 +116,10 @@ Model make_model(const elbm_params &P) {
   M.charge_model = P.charge_model;
   M.newton_max = P.newton_max;
   M.alpha_guess = P.alpha_guess;
+  M.strict = P.strict;
+  M.alpha_iter = P.alpha_iter;
+  M.sor_check_every = P.sor_check_every;
+  M.sor_tol = P.sor_tol;
   for (int s = 0; s < 2; ++s)
     for (int t = 0; t < 2; ++t) {
       M.G[s][t] = P.G[s][t];
@@ -162,6 +166,8 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.boxes = (const BoxDev *)(b + c->o_boxes);
   a.block_box = (const int32_t *)(b + c->o_bb);
   a.partials = (double *)(b + c->o_part);
+  a.res_part = (double *)(b + c->o_rpart);
+  a.fel_part = (double *)(b + c->o_fpart);
   a.scal = (double *)(b + c->o_scal);
   a.cnt = (unsigned long long *)(b + c->o_cnt);
   a.err = (uint32_t *)(b + c->o_err);
@@ -262,9 +268,24 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M, a.prio);
   hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 2);
-  for (int sw = 0; sw < c->P.sor_sweeps; ++sw) {
-    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0);
-    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1);
+  // red-black sweeps; with a tolerance the FP64 residual is checked after
+  // every sor_check_every sweeps (boxes within it skip the rest) and after
+  // the last one, which recorded steps always take (diagnostics)
+  const int nsw = c->P.sor_sweeps, every = c->P.sor_check_every;
+  const bool tol = c->P.sor_tol > 0.0, checks = tol && every > 0;
+  for (int sw = 1; sw <= nsw; ++sw) {
+    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0, (int)checks);
+    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1, (int)checks);
+    if (checks && sw % every == 0 && sw < nsw) {
+      hipLaunchKernelGGL((k_residual<T, F>), grid, blk, 0, c->stream, a, 1);
+      hipLaunchKernelGGL(k_res_box, dim3(nb), blk, 0, c->stream, a.boxes, (const double *)a.res_part, a.scal, a.cnt,
+                         a.err, c->P.sor_tol, sw, 0, a.prio);
+    }
+  }
+  if (tol || rec) {
+    hipLaunchKernelGGL((k_residual<T, F>), grid, blk, 0, c->stream, a, (int)checks);
+    hipLaunchKernelGGL(k_res_box, dim3(nb), blk, 0, c->stream, a.boxes, (const double *)a.res_part, a.scal, a.cnt,
+                       a.err, c->P.sor_tol, nsw, 1, a.prio);
   }
   if (c->any_gauge) {
     hipLaunchKernelGGL((k_phi_partials<T, F>), grid, blk, 0, c->stream, a);
@@ -338,7 +359,6 @@ elbm_status set_box_impl(elbm_ctx *c, int box, const uint8_t *type, const double
   const BoxDev &B = c->bdev[box];
   const int C = c->P.ncomp;
   const size_t nb = (size_t)B.n;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->base + c->o_type + B.off, type, nb, hipMemcpyHostToDevice));
   // stage planes: rho [C], u [3], u_bc [3], xi (one at a time)
   for (int s = 0; s < C; ++s)
@@ -466,6 +486,9 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   if (P->storage != ELBM_STORAGE_F64 && P->storage != ELBM_STORAGE_F32 && P->storage != ELBM_STORAGE_F32_ALL)
     return ELBM_EINVAL;
   if (P->sor_sweeps < 0 || P->newton_max < 1 || P->newton_max > 1000) return ELBM_EINVAL;
+  if (!(P->sor_tol >= 0.0) || P->sor_check_every < 0) return ELBM_EINVAL;
+  if (P->strict < 0 || P->strict > (ELBM_STRICT_NEGPOP | ELBM_STRICT_ALPHA)) return ELBM_EINVAL;
+  if (P->alpha_iter != ELBM_ITER_NEWTON && P->alpha_iter != ELBM_ITER_HALLEY) return ELBM_EINVAL;
   if (P->charge_model != ELBM_CHARGE_CONSERVING && P->charge_model != ELBM_CHARGE_GENERATOR) return ELBM_EINVAL;
   if (!(P->w_theta > 0.0) || !(P->K_d > 0.0) || !(P->nu0 > 0.0) || !(P->newton_rtol > 0.0)) return ELBM_EINVAL;
   if (P->carreau && !(P->nu_inf > 0.0 && P->lam >= 0.0)) return ELBM_EINVAL;
@@ -546,6 +569,8 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_boxes = take(sizeof(BoxDev) * nboxes);
   c->o_bb = take(sizeof(int32_t) * c->nblocks);
   c->o_part = take(sizeof(double) * 4 * (size_t)c->nblocks);
+  c->o_rpart = take(sizeof(double) * 2 * (size_t)c->nblocks);
+  c->o_fpart = take(sizeof(double) * 3 * (size_t)c->nblocks);
   c->o_scal = take(sizeof(double) * NSCAL * nboxes);
   c->o_cnt = take(sizeof(unsigned long long) * NCNT * nboxes);
   c->o_err = take(sizeof(uint32_t) * 4);
@@ -613,6 +638,9 @@ elbm_status elbm_set_box(elbm_ctx *c, int32_t box, const uint8_t *type, const do
   elbm_status st = check_box_arg(c, box);
   if (st) return st;
   if (!type || !rho) return fail(c, ELBM_EINVAL, "node_type and rho are required");
+  // steps in flight read the box table and may run a captured graph: finish
+  // them before the graphs are dropped and the box record is rewritten
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   BoxDev &B = c->bdev[box];
   int64_t nu = 0;
   bool dir = false;
@@ -755,7 +783,10 @@ elbm_status elbm_sync(elbm_ctx *c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   uint32_t e = 0;
   HIPCHK(c, hipMemcpy(&e, c->base + c->o_err, sizeof(e), hipMemcpyDeviceToHost));
-  if (e & 1u) return fail(c, ELBM_ENONFINITE, "a post-collision population became non-finite");
+  if (e & ERR_NONFINITE) return fail(c, ELBM_ENONFINITE, "a post-collision population became non-finite");
+  if (e & ERR_NEGPOP) return fail(c, ELBM_ENEGPOP, "a post-collision population became negative (strict)");
+  if (e & ERR_SOR) return fail(c, ELBM_ENOCONV, "a Poisson solve ended above sor_tol");
+  if (e & ERR_ALPHA) return fail(c, ELBM_ENOCONV, "an alpha solve fell back: no root or no convergence (strict)");
   return ELBM_OK;
 }
 
@@ -843,40 +874,42 @@ elbm_status elbm_diagnostics(elbm_ctx *c, int32_t box, elbm_diag *out) {
   } break)
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<double> part((size_t)nblk * 5);
+  // block partials in block order (a fixed-order sum, reproducible)
+  std::vector<double> part((size_t)nblk * DIAG_W);
   HIPCHK(c, hipMemcpy(part.data(), dst, part.size() * 8, hipMemcpyDeviceToHost));
+  double asum = 0.0, acnt = 0.0, amin = INFINITY, amax = -INFINITY;
   for (int i = 0; i < nblk; ++i) {
-    out->mass[0] += part[i * 5 + 0];
-    out->mass[1] += part[i * 5 + 1];
-    for (int d = 0; d < 3; ++d) out->momentum[d] += part[i * 5 + 2 + d];
+    const double *v = part.data() + (size_t)i * DIAG_W;
+    out->mass[0] += v[0];
+    out->mass[1] += v[1];
+    for (int d = 0; d < 3; ++d) out->momentum[d] += v[2 + d];
+    asum += v[5];
+    acnt += v[6];
+    amin = fmin(amin, -v[7]);
+    amax = fmax(amax, v[8]);
   }
+  out->alpha_min = acnt > 0.0 ? amin : 0.0;
+  out->alpha_max = acnt > 0.0 ? amax : 0.0;
+  out->alpha_mean = acnt > 0.0 ? asum / acnt : 0.0;
+  // electric force of the last recorded step: the box's block partials in order
+  std::vector<double> fp((size_t)B.nblocks * 3);
+  HIPCHK(c, hipMemcpy(fp.data(), (double *)(c->base + c->o_fpart) + (size_t)B.first_block * 3, fp.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (int i = 0; i < B.nblocks; ++i)
+    for (int d = 0; d < 3; ++d) out->sum_Fel[d] += fp[(size_t)i * 3 + d];
+  double sc[NSCAL];
+  HIPCHK(c, hipMemcpy(sc, c->base + c->o_scal + sizeof(double) * NSCAL * box, sizeof(sc), hipMemcpyDeviceToHost));
+  out->sor_residual = sc[4];
+  out->sor_scale = sc[5];
+  out->sor_sweeps = (int32_t)sc[6];
   unsigned long long cn[NCNT];
   HIPCHK(c, hipMemcpy(cn, c->base + c->o_cnt + sizeof(unsigned long long) * NCNT * box, sizeof(cn), hipMemcpyDeviceToHost));
   out->n_fallback = (int64_t)cn[0];
   out->n_negative = (int64_t)cn[2];
   out->n_collisions = (int64_t)cn[4];
+  out->n_sor_noconv = (int64_t)cn[5];
   const int64_t solved = (int64_t)cn[4] - (int64_t)cn[0];
   out->mean_newton_iters = solved > 0 ? (double)cn[1] / (double)solved : 0.0;
-  // alpha statistics of the last recorded step over fluid nodes
-  std::vector<double> al((size_t)B.n);
-  std::vector<uint8_t> ty((size_t)B.n);
-  HIPCHK(c, hipMemcpy(ty.data(), c->base + c->o_type + B.off, (size_t)B.n, hipMemcpyDeviceToHost));
-  double mn = INFINITY, mx = -INFINITY, sm = 0.0;
-  int64_t cntn = 0;
-  for (int s = 0; s < c->P.ncomp; ++s) {
-    HIPCHK(c, hipMemcpy(al.data(), (double *)(c->base + c->o_reca) + (int64_t)s * c->Ntot + B.off, (size_t)B.n * 8,
-                        hipMemcpyDeviceToHost));
-    for (int i = 0; i < B.n; ++i)
-      if ((ty[i] & 3) == K_FLUID) {
-        mn = fmin(mn, al[i]);
-        mx = fmax(mx, al[i]);
-        sm += al[i];
-        ++cntn;
-      }
-  }
-  out->alpha_min = cntn ? mn : 0.0;
-  out->alpha_max = cntn ? mx : 0.0;
-  out->alpha_mean = cntn ? sm / (double)cntn : 0.0;
   return ELBM_OK;
 }
 

@@ -39,16 +39,23 @@ struct BoxDev {
 };
 
 struct Model {
-  int32_t C, carreau, curvature, electrostriction, charge_model, newton_max, alpha_guess, pad;
+  int32_t C, carreau, curvature, electrostriction, charge_model, newton_max, alpha_guess, strict;
+  int32_t alpha_iter, sor_check_every;
   double G[2][2], Gw[2][2], nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
   double rho_in[2], rho_out[2];
+  double sor_tol;
 };
 
 // scalars per box: [0] charge scale of the bulk part, [1] of the surface
-// part, [2] neutralising charge qbar, [3] mean potential
+// part, [2] neutralising charge qbar, [3] mean potential, [4] Poisson
+// residual of the last check, [5] its scale max|rhs|, [6] sweeps done at
+// that check, [7] 1 once this step's solve has met its tolerance
 constexpr int NSCAL = 8;
-// counters per box: fallbacks, Newton updates, negative f, non-finite f, collisions
+// counters per box: fallbacks, Newton updates, negative f, non-finite f,
+// collisions, Poisson solves above their tolerance
 constexpr int NCNT = 8;
+// bits of the sticky error word
+constexpr uint32_t ERR_NONFINITE = 1u, ERR_NEGPOP = 2u, ERR_ALPHA = 4u, ERR_SOR = 8u;
 
 // T: population storage type, F: field storage / stencil arithmetic type
 template <typename T, typename F>
@@ -65,6 +72,8 @@ struct Ptrs {
   const BoxDev *boxes;
   const int32_t *block_box;
   double *partials;     // [nblocks][4]
+  double *res_part;     // [nblocks][2] Poisson residual and max|rhs| per block
+  double *fel_part;     // [nblocks][3] electric force summed per block (recorded steps)
   double *scal;         // [nboxes][NSCAL]
   unsigned long long *cnt;  // [nboxes][NCNT]
   uint32_t *err;
@@ -191,6 +200,27 @@ __device__ __forceinline__ void block_sum_store(double (&v)[K], double *out) {
     double s = sm[0][threadIdx.x];
 #pragma unroll
     for (int w = 1; w < BLK / 64; ++w) s += sm[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// Block maxima of K non-negative doubles (waves, then the four wave results).
+template <int K>
+__device__ __forceinline__ void block_max_store(double (&v)[K], double *out) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], off, 64));
+  __shared__ double sm[BLK / 64][K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sm[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = sm[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < BLK / 64; ++w) s = fmax(s, sm[w][threadIdx.x]);
     out[threadIdx.x] = s;
   }
 }
@@ -467,16 +497,20 @@ __device__ __forceinline__ double alpha_g_top(const T *f, const double *xs, doub
   return S + amax * L;
 }
 
-// Newton on g from a inside (0, amax) (f, xs as for the set-up pass).  The
-// first step that would leave the interval at the top checks that a root
-// exists at all (alpha_g_top); none: the fallback at once.
+// Newton (or Halley) on g from a inside (0, amax) (f, xs as for the set-up
+// pass).  The first step that would leave the interval at the top checks that
+// a root exists at all (alpha_g_top); none: the fallback at once.  Halley's
+// step a - 2 g g' / (2 g'^2 - g g'') uses g'' = sum_p f_p x_p^2 / (1 + a x_p)
+// (one reciprocal per direction, no logarithm); where its denominator is not
+// positive the Newton step is taken.  The Taylor bound that skips the final
+// evaluation holds for Newton steps only.
 template <typename T>
 __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double M2,
-                                                double a, double rtol, int maxit, int &iters) {
+                                                double a, double rtol, int maxit, int &iters, bool halley) {
   {
     bool probed = false;
     for (int it = 0; it <= maxit; ++it) {
-      double S = 0.0, gp = L;
+      double S = 0.0, gp = L, gpp = 0.0;
 #pragma unroll 4
       for (int p = 0; p < NQ; ++p) {
         const double fp = double(f[p * BLK]);
@@ -485,6 +519,7 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
         const double l = log1p_fast(y);
         S += fp * phi_of(y, l);
         gp += (x * fp) * l;
+        if (halley) gpp += (x * fp) * x * rcp_nr(1.0 + y);
       }
       const double g = S + a * L;
       if (fabs(g) <= rtol * S) {
@@ -493,15 +528,26 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
       }
       if (it == maxit) break;
       double an = (gp > 0.0) ? a - g / gp : 2.0 * a;
-      const bool newton = gp > 0.0 && an > 0.0 && an < amax;
+      bool newton = gp > 0.0 && an > 0.0 && an < amax;
+      if (halley && gp > 0.0) {
+        const double den = 2.0 * gp * gp - g * gpp;
+        if (den > 0.0) {
+          an = a - 2.0 * g * gp / den;
+          newton = false;
+        }
+      }
       if (an >= amax) {
         if (!probed) {
           probed = true;
           if (!(alpha_g_top<T>(f, xs, L, amax) > 0.0)) break;
         }
         an = 0.5 * (a + amax);
+        newton = false;
       }
-      if (an <= 0.0) an = 0.5 * a;
+      if (an <= 0.0) {
+        an = 0.5 * a;
+        newton = false;
+      }
       if (fabs(an - a) <= 4.0 * 2.220446049250313e-16 * a) {
         iters = it + 1;
         return an;
@@ -525,12 +571,13 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
 
 template <typename T>
 __device__ __forceinline__ double alpha_newton(const T *f, const double *xs, AlphaSetup st, double a0, double rtol,
-                                               int maxit, int &iters) {
+                                               int maxit, int &iters, bool halley = false) {
   if (st.state == 1 || st.state == 3) {
     iters = 0;
     return st.state == 1 ? 2.0 : st.a;
   }
-  if (st.state == 0) return alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), rtol, maxit, iters);
+  if (st.state == 0)
+    return alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), rtol, maxit, iters, halley);
   iters = -1;
   return fmin(2.0, 0.99 * st.amax);
 }

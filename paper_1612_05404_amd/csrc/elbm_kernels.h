@@ -193,6 +193,7 @@ __global__ __launch_bounds__(BLK) void k_charge_coef(const BoxDev *boxes, const 
     o[0] = cb;
     o[1] = cs;
     o[2] = B.n_unknown > 0 ? (cb * tot[2] + cs * tot[3]) / (double)B.n_unknown : 0.0;
+    o[7] = 0.0;  // this step's Poisson solve has not met its tolerance yet
   }
 }
 
@@ -227,11 +228,13 @@ __global__ __launch_bounds__(BLK) void k_charge_rhs(Ptrs<T, F> a) {
 // Every load is issued before the Dirichlet test (one dependent memory round
 // trip less); faces leaving the box are skipped.
 template <typename T, typename F>
-__global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
+__global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour, int skip_converged) {
   Node nd;
   decode(a, nd);
   field_chain_priority(a.prio);  // after the uniform loads of decode
   if (!nd.live) return;
+  // a box whose solve met its tolerance at a check keeps its potential
+  if (skip_converged && a.scal[(int64_t)nd.bb * NSCAL + 7] != 0.0) return;
   if (((nd.x + nd.y + nd.z) & 1) != colour) return;
   const uint8_t tt = a.type[nd.g];
   const F rc = a.rho[nd.g], pc = a.phi[nd.g], rhs = a.rhs[nd.g];
@@ -257,6 +260,75 @@ __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour) {
   }
   const F om = F(nd.B.omega);
   a.phi[nd.g] = (F(1) - om) * pc + om * (Bs - rhs) / A;
+}
+
+// Poisson residual of every unknown node in FP64,
+//   r = sum_faces eps_f (phi_nb - phi) - rhs   (faces leaving the box skipped),
+// and the block maxima of |r| and |rhs|.  Boxes whose solve already met its
+// tolerance this step are skipped (skip_converged).
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_residual(Ptrs<T, F> a, int skip_converged) {
+  Node nd;
+  decode(a, nd);
+  field_chain_priority(a.prio);  // after the uniform loads of decode
+  double v[2] = {0.0, 0.0};
+  bool on = nd.live && !(skip_converged && a.scal[(int64_t)nd.bb * NSCAL + 7] != 0.0);
+  if (on) on = !(a.type[nd.g] & B_DIRICHLET);
+  if (on) {
+    const double ec = 1.0 + double(a.rho[nd.g]);
+    const double pc = double(a.phi[nd.g]);
+    double acc = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int m = nbr(nd.B, nd.x, nd.y, nd.z, kFace[f][0], kFace[f][1], kFace[f][2]);
+      if (m < 0) continue;
+      const int64_t gm = nd.B.off + m;
+      acc += 0.5 * (ec + (1.0 + double(a.rho[gm]))) * (double(a.phi[gm]) - pc);
+    }
+    const double rhs = double(a.rhs[nd.g]);
+    v[0] = fabs(acc - rhs);
+    v[1] = fabs(rhs);
+  }
+  block_max_store<2>(v, a.res_part + (int64_t)nd.blk * 2);
+}
+
+// One block per box: the box's residual and scale from the block maxima.
+// A check (final == 0) with the residual within sor_tol * max|rhs| marks the
+// box's solve as done (later sweeps skip it); the final call records the
+// sweeps of a box still running and counts (and, with a tolerance, flags) a
+// solve that ends above it.  A box done at a check keeps that check's record.
+__global__ __launch_bounds__(BLK) void k_res_box(const BoxDev *boxes, const double *res_part, double *scal,
+                                                 unsigned long long *cnt, uint32_t *err, double tol, int done,
+                                                 int final, int prio) {
+  const BoxDev B = boxes[blockIdx.x];
+  field_chain_priority(prio);  // after the uniform box load
+  double *o = scal + (int64_t)blockIdx.x * NSCAL;
+  if (o[7] != 0.0) return;
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < B.nblocks; i += BLK) {
+    v[0] = fmax(v[0], res_part[(int64_t)(B.first_block + i) * 2]);
+    v[1] = fmax(v[1], res_part[(int64_t)(B.first_block + i) * 2 + 1]);
+  }
+  __shared__ double tot[2];
+  block_max_store<2>(v, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    o[4] = tot[0];
+    o[5] = tot[1];
+    const bool ok = tot[0] <= tol * tot[1];
+    if (!final) {
+      if (tol > 0.0 && ok) {
+        o[6] = double(done);
+        o[7] = 1.0;
+      }
+    } else {
+      o[6] = double(done);
+      if (tol > 0.0 && !ok) {
+        atomicAdd(cnt + (int64_t)blockIdx.x * NCNT + 5, 1ull);
+        atomicOr(err, ERR_SOR);
+      }
+    }
+  }
 }
 
 // Zero-mean gauge of the potential for boxes without Dirichlet nodes.
@@ -328,7 +400,7 @@ __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, dou
   }
 }
 
-// Velocity inlet (the jet set-up of Sec. IV: Poiseuille velocity at the inlet
+// Velocity inlet (the jet set-up of Sec. III.B: Poiseuille velocity at the inlet
 // nodes, density that of the liquid): each step an inlet node is reset to
 // f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted mean density of its
 // fluid neighbours (rho_in when it has none).  Written to the output buffer,
@@ -450,7 +522,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
       // ---- alpha: Newton polish from the starter
       const double uu = ux * ux + uy * uy + uz * uz;
       int its;
-      const double al = alpha_newton<T>(f, xs, st, a0, M.rtol, M.newton_max, its);
+      const double al = alpha_newton<T>(f, xs, st, a0, M.rtol, M.newton_max, its, M.alpha_iter == ELBM_ITER_HALLEY);
       c_col += 1;
       if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
       // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root,
@@ -502,6 +574,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
     if (c_fb) atomicAdd(cn + 0, c_fb);
     if (c_it) atomicAdd(cn + 1, c_it);
     if (c_col) atomicAdd(cn + 4, c_col);
+    if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(a.err, ERR_ALPHA);
   }
 }
 
@@ -649,15 +722,23 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     a.rec_u[2 * a.N + nd.g] = r > 0.0 ? F(m2 / r) : F(0);
   }
   if (nd.live && k == K_INLET) inlet_store<T, F, C>(a, M, nd);
+  // ---- recorded steps: the electric force summed per block (fixed order)
+  if (record) {
+    double fe[3] = {double(Fel[0]), double(Fel[1]), double(Fel[2])};
+    block_sum_store<3>(fe, a.fel_part + (int64_t)nd.blk * 3);
+  }
   // ---- counters: wave sums, one atomic per wave and counter
   c_neg = wave_sum_u64(c_neg);
   c_nf = wave_sum_u64(c_nf);
   if (lane == 0) {
     unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
-    if (c_neg) atomicAdd(cn + 2, c_neg);
+    if (c_neg) {
+      atomicAdd(cn + 2, c_neg);
+      if (M.strict & ELBM_STRICT_NEGPOP) atomicOr(a.err, ERR_NEGPOP);
+    }
     if (c_nf) {
       atomicAdd(cn + 3, c_nf);
-      atomicOr(a.err, 1u);
+      atomicOr(a.err, ERR_NONFINITE);
     }
   }
 }
@@ -761,26 +842,42 @@ __global__ __launch_bounds__(BLK) void k_from_double(const double *src, X *dst, 
   }
 }
 
-// Mass and momentum partial sums of one box's current populations.
+// Partial sums of one box per block, out[blk][9]: mass per component and
+// momentum of the current populations, then over the fluid (node,
+// component) pairs of the last recorded step the sum and count of alpha,
+// -min alpha and max alpha (maxima of non-negative values: alpha > 0).
+constexpr int DIAG_W = 9;
 template <typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_diag(Ptrs<T, F> a, int box, double *out) {
   const BoxDev B = a.boxes[box];
   const int n = blockIdx.x * BLK + threadIdx.x;
-  double v5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double mm[2] = {-INFINITY, -INFINITY};
   if (n < B.n) {
     const int64_t g = B.off + n;
 #pragma unroll
     for (int s = 0; s < C; ++s)
 #pragma unroll
       for (int p = 0; p < NQ; ++p) {
-        const double v = double(a.fa[(int64_t)(s * NQ + p) * a.N + g]);
-        v5[s] += v;
-        v5[2] += kCx[p] * v;
-        v5[3] += kCy[p] * v;
-        v5[4] += kCz[p] * v;
+        const double f = double(a.fa[(int64_t)(s * NQ + p) * a.N + g]);
+        v[s] += f;
+        v[2] += kCx[p] * f;
+        v[3] += kCy[p] * f;
+        v[4] += kCz[p] * f;
+      }
+    if ((a.type[g] & 3) == K_FLUID)
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        const double al = a.rec_alpha[(int64_t)s * a.N + g];
+        v[5] += al;
+        v[6] += 1.0;
+        mm[0] = fmax(mm[0], -al);
+        mm[1] = fmax(mm[1], al);
       }
   }
-  block_sum_store<5>(v5, out + (int64_t)blockIdx.x * 5);
+  block_sum_store<7>(v, out + (int64_t)blockIdx.x * DIAG_W);
+  __syncthreads();
+  block_max_store<2>(mm, out + (int64_t)blockIdx.x * DIAG_W + 7);
 }
 
 }  // namespace elbm

@@ -17,11 +17,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelbm.so")
 
 ELBM_OK, ELBM_EINVAL, ELBM_ENOMEM, ELBM_EHIP, ELBM_ENONFINITE, ELBM_ESTATE = 0, -1, -2, -3, -4, -7
+ELBM_ENEGPOP, ELBM_ENOCONV = -5, -6
+STRICT_NEGPOP, STRICT_ALPHA = 1, 2
 STORAGE_F64, STORAGE_F32, STORAGE_F32_ALL = 0, 1, 2
 # dtype names: "f64" all FP64; "f32" FP32 populations + FP64 fields; "f32all" all FP32
 STORAGE = {"f64": STORAGE_F64, "f32": STORAGE_F32, "f32all": STORAGE_F32_ALL}
 # initial guess of the alpha Newton iteration (every guess is polished to the same rule)
 GUESS = {"standard": 0, "mlp": 1, "series": 2}
+# the alpha iteration (same stopping rule): Newton, or Halley with g''
+ITER = {"newton": 0, "halley": 1}
 Q = 19
 
 
@@ -35,11 +39,12 @@ class elbm_params(ct.Structure):
     _fields_ = [
         ("ncomp", ct.c_int32), ("storage", ct.c_int32), ("carreau", ct.c_int32), ("curvature", ct.c_int32),
         ("electrostriction", ct.c_int32), ("charge_model", ct.c_int32), ("sor_sweeps", ct.c_int32),
-        ("newton_max", ct.c_int32), ("alpha_guess", ct.c_int32), ("pad_", ct.c_int32),
+        ("newton_max", ct.c_int32), ("alpha_guess", ct.c_int32), ("strict", ct.c_int32),
         ("G", (ct.c_double * 2) * 2), ("Gw", (ct.c_double * 2) * 2),
         ("nu0", ct.c_double), ("nu_inf", ct.c_double), ("lam", ct.c_double), ("K_d", ct.c_double),
         ("rho_th", ct.c_double), ("w_theta", ct.c_double), ("xi_b", ct.c_double), ("xi_s", ct.c_double),
         ("newton_rtol", ct.c_double), ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
+        ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("alpha_iter", ct.c_int32),
     ]
 
 
@@ -61,7 +66,9 @@ class elbm_diag(ct.Structure):
         ("mass", ct.c_double * 2), ("momentum", ct.c_double * 3),
         ("alpha_min", ct.c_double), ("alpha_max", ct.c_double), ("alpha_mean", ct.c_double),
         ("mean_newton_iters", ct.c_double), ("n_fallback", ct.c_int64), ("n_negative", ct.c_int64),
-        ("n_collisions", ct.c_int64),
+        ("n_collisions", ct.c_int64), ("sum_Fel", ct.c_double * 3), ("sor_residual", ct.c_double),
+        ("sor_scale", ct.c_double), ("sor_sweeps", ct.c_int32), ("pad_", ct.c_int32),
+        ("n_sor_noconv", ct.c_int64),
     ]
 
 
@@ -79,7 +86,7 @@ TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
-ABI_VERSION = 3  # include/elbm.h ELBM_ABI_VERSION
+ABI_VERSION = 4  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -135,12 +142,16 @@ def load(path: str = LIB_PATH):
     return L
 
 
-def make_params(p, storage: int, guess: int = 0) -> elbm_params:
+def make_params(p, storage: int, guess: int = 0, alpha_iter: int = 0, strict: int = 0) -> elbm_params:
     P = elbm_params()
     P.ncomp, P.storage = int(p.ncomp), int(storage)
     P.carreau, P.curvature, P.electrostriction = int(p.carreau), int(p.curvature), int(p.electrostriction)
     P.charge_model, P.sor_sweeps, P.newton_max = int(p.charge_model), int(p.sor_sweeps), int(p.newton_max)
     P.alpha_guess = int(guess)
+    P.alpha_iter = int(alpha_iter)
+    P.strict = int(strict)
+    P.sor_tol = float(getattr(p, "sor_tol", 0.0))
+    P.sor_check_every = int(getattr(p, "sor_check_every", 0))
     gw = p.G if p.Gw is None else p.Gw
     for s in range(2):
         for t in range(2):
@@ -182,7 +193,7 @@ class Lattice:
     alpha is FP64 in every mode."""
 
     def __init__(self, params, boxes: Sequence, dtype: str = "f64", device: str = "cuda:0",
-                 stream=None, alpha_guess: str = "standard"):
+                 stream=None, alpha_guess: str = "standard", alpha_iter: str = "newton", strict: int = 0):
         import torch
         self.L = load()
         self.params = params
@@ -193,7 +204,9 @@ class Lattice:
         storage = STORAGE[dtype]
         if alpha_guess not in GUESS:
             raise ValueError(f"alpha_guess must be one of {sorted(GUESS)}")
-        self._P = make_params(params, storage, GUESS[alpha_guess])
+        if alpha_iter not in ITER:
+            raise ValueError(f"alpha_iter must be one of {sorted(ITER)}")
+        self._P = make_params(params, storage, GUESS[alpha_guess], ITER[alpha_iter], strict)
         self._B = (elbm_box * len(self.boxes))(*[make_box(params, b) for b in self.boxes])
         h = ct.c_void_p()
         self._check(self.L.elbm_create(ct.byref(self._P), self._B, len(self.boxes), ct.byref(h)), None)
@@ -295,7 +308,9 @@ class Lattice:
         self._check(self.L.elbm_diagnostics(self.h, i, ct.byref(d)))
         return dict(mass=list(d.mass), momentum=list(d.momentum), alpha_min=d.alpha_min,
                     alpha_max=d.alpha_max, alpha_mean=d.alpha_mean, mean_newton_iters=d.mean_newton_iters,
-                    n_fallback=d.n_fallback, n_negative=d.n_negative, n_collisions=d.n_collisions)
+                    n_fallback=d.n_fallback, n_negative=d.n_negative, n_collisions=d.n_collisions,
+                    sum_Fel=list(d.sum_Fel), sor_residual=d.sor_residual, sor_scale=d.sor_scale,
+                    sor_sweeps=d.sor_sweeps, n_sor_noconv=d.n_sor_noconv)
 
     def set_graphs(self, enable: bool = True):
         self._check(self.L.elbm_set_graphs(self.h, int(bool(enable))))

@@ -37,7 +37,34 @@ def test_exports_every_declared_symbol(lib):
 
 def test_abi_version(lib):
     from paper_1612_05404_amd import elbm
-    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 3
+    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 4
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's structures have the sizes and field offsets the C compiler
+    # gives the header's (a small C program built against include/elbm.h)
+    import os
+    import subprocess
+    from paper_1612_05404_amd import elbm
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"elbm_params": elbm.elbm_params, "elbm_box": elbm.elbm_box, "elbm_diag": elbm.elbm_diag,
+               "elbm_launch": elbm.elbm_launch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "elbm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ct.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(out[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
 
 
 def _params(**kw):
@@ -69,7 +96,8 @@ def test_create_and_layout_without_gpu(lib):
 
 
 @pytest.mark.parametrize("field,value", [("ncomp", 3), ("storage", 5), ("sor_sweeps", -1), ("newton_max", 0),
-                                         ("charge_model", 7), ("alpha_guess", 9)])
+                                         ("charge_model", 7), ("alpha_guess", 9), ("strict", 4), ("strict", -1),
+                                         ("alpha_iter", 2), ("sor_tol", -1e-3), ("sor_check_every", -2)])
 def test_create_rejects_bad_params(lib, field, value):
     P, p = _params()
     setattr(P, field, value)

@@ -99,28 +99,33 @@ def test_ensemble_fp64_matches_oracle(elbm):
 
 
 def test_full_ensemble_sampled(elbm):
-    # The full 256-box ensemble (27.5 M nodes, FP32) in the launch mapping the
-    # autotuner picks for it (XCD-aware order, 2-step graphs), 8 steps: the
-    # smallest and largest boxes equal the same boxes run alone bit for bit,
-    # and the first 24^3 box matches the FP64 oracle at the FP32 bar.
+    # The full 256-box ensemble (27.5 M nodes, FP32, learned starter with the
+    # stored network) in an XCD-aware mapping with 8x4x8 alpha tiles, 100
+    # steps: a 24^3 and a 64^3 box equal the same boxes run alone bit for bit,
+    # and both match the FP64 oracle at the FP32 bar.
     import oracle as ora
     from test_gpu_parity import compare
+    from paper_1612_05404_amd import learned
     wl = inputs.ensemble()
     edges = [b.nx for b in wl.boxes]
     i24, i64 = edges.index(24), edges.index(64)
-    _say(f"[gpu ensemble] full: {len(wl.boxes)} boxes, {wl.nodes} nodes, 8 steps; sampled boxes {i24}, {i64}")
-    lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-    lat.set_launch(1, 2, 1)
-    lat.step(8, record=True)
+    _say(f"[gpu ensemble] full: {len(wl.boxes)} boxes, {wl.nodes} nodes, 100 steps; sampled boxes {i24}, {i64}")
+    w = learned.load_weights()
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess="mlp")
+    lat.mlp_set_weights(w)
+    lat.set_launch(1, 4, 2)
+    lat.step(100, record=True)
     lat.sync()
     for i in (i24, i64):
-        one = elbm.Lattice(wl.params, [wl.boxes[i]], "f32")
-        one.step(8, record=True)
+        one = elbm.Lattice(wl.params, [wl.boxes[i]], "f32", alpha_guess="mlp")
+        one.mlp_set_weights(w)
+        one.step(100, record=True)
         assert _same(_fields(lat, i), _fields(one, 0)), f"box {i} differs"
         one.close()
-    o = ora.Oracle(wl.params, wl.boxes[i24], nthreads=NTHREADS)
-    o.step(8)
-    compare(lat, i24, o, 1e-5)
+        o = ora.Oracle(wl.params, wl.boxes[i], nthreads=NTHREADS)
+        o.step(100)
+        _say(f"    box {i} ({edges[i]}^3) vs oracle")
+        compare(lat, i, o, 1e-5, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi"))
     lat.close()
 
 

@@ -248,13 +248,12 @@ def test_learned_starter_parity_and_fewer_iterations(elbm):
     a0, i0, d0 = res["standard"]
     a1, i1, d1 = res["mlp"]
     _, i2, d2 = res["series"]
-    both = (i0 >= 0) & (i1 >= 0) & (a0 > 0)
-    err = np.abs(a1 - a0)[both] / a0[both]
+    from test_gpu_parity import check_alpha
+    check_alpha(a1, i1, a0, i0, label="alpha learned vs plain")
     sv = served & (i1 >= 0) & (i2 >= 0)
-    _say(f"    alpha learned vs plain: max rel {err.max():.2e}; mean updates standard {d0['mean_newton_iters']:.4f} "
+    _say(f"    mean updates standard {d0['mean_newton_iters']:.4f} "
          f"series {d2['mean_newton_iters']:.4f} learned {d1['mean_newton_iters']:.4f}; on the {int(sv.sum())} "
          f"served nodes series {i2[sv].mean():.3f} learned {i1[sv].mean():.3f}")
-    assert np.quantile(err, 0.999) < 1e-9
     assert d1["n_fallback"] <= d0["n_fallback"]
     assert d1["mean_newton_iters"] < 0.5 * d0["mean_newton_iters"]
     assert d1["mean_newton_iters"] <= d2["mean_newton_iters"]
@@ -278,13 +277,12 @@ def test_stored_network_on_field_drop(elbm):
     a0, i0, d0 = res["standard"]
     a1, i1, d1 = res["mlp"]
     _, i2, d2 = res["series"]
-    both = (i0 >= 0) & (i1 >= 0) & (a0 > 0)  # alpha is 0 at non-fluid nodes
-    err = np.abs(a1 - a0)[both] / a0[both]
+    from test_gpu_parity import check_alpha
+    check_alpha(a1, i1, a0, i0, label="alpha learned vs plain")  # alpha is 0 at non-fluid nodes
     sv = served & (i1 >= 0) & (i2 >= 0)
-    _say(f"    alpha max rel diff {err.max():.2e}; mean updates standard {d0['mean_newton_iters']:.4f} "
+    _say(f"    mean updates standard {d0['mean_newton_iters']:.4f} "
          f"series {d2['mean_newton_iters']:.4f} learned {d1['mean_newton_iters']:.4f}; on the {int(sv.sum())} "
          f"served nodes series {i2[sv].mean():.3f} learned {i1[sv].mean():.3f}")
-    assert np.quantile(err, 0.999) < 1e-9
     assert d1["mean_newton_iters"] <= d2["mean_newton_iters"] < d0["mean_newton_iters"]
     if sv.sum() > 50:
         assert i1[sv].mean() < i2[sv].mean()

@@ -56,6 +56,20 @@ def compare(lat, i, o, tol, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi", "q"
     return errs
 
 
+def check_alpha(al, it, oal, oit, tol=1e-11, label="alpha"):
+    """Alpha of two solvers on the same states: the same fallback nodes, and
+    the largest relative difference over every node both solved within tol."""
+    fb, ofb = it < 0, oit < 0
+    both = (it >= 0) & (oit >= 0) & (oal > 0)
+    err = np.abs(al - oal)[both] / oal[both]
+    emax = float(err.max()) if err.size else 0.0
+    _say(f"    {label}: max rel err {emax:.2e} over {int(both.sum())} solves; fallbacks {int(fb.sum())} / "
+         f"{int(ofb.sum())}; update counts equal {np.mean(it == oit):.4f}")
+    assert np.array_equal(fb, ofb), "fallback nodes differ"
+    assert emax <= tol, emax
+    return emax
+
+
 def run_both(elbm, params, boxes, dtype, steps, name, launch=None, guess=None):
     import oracle as ora
     _say(f"[gpu parity] {name}: dtype={dtype} steps={steps} boxes={[(b.nx, b.ny, b.nz) for b in boxes]}"
@@ -80,13 +94,8 @@ def test_drop32_fp64_parity_100_steps(elbm):
     compare(lat, 0, o, 1e-12)
     import oracle as ora
     al, it = lat.read_alpha(0)
-    oal, oit = o.field(ora.F_ALPHA), o.iters()
-    both = (it >= 0) & (oit >= 0)
-    err = np.abs(al - oal)[both] / oal[both]
-    _say(f"    alpha: max rel err {err.max():.2e}, fallback nodes gpu {int((it < 0).sum())} oracle {int((oit < 0).sum())}, "
-         f"iters equal {np.mean(it == oit):.4f}")
-    assert np.quantile(err, 0.999) < 1e-9
-    assert np.mean(it == oit) > 0.99
+    check_alpha(al, it, o.field(ora.F_ALPHA), o.iters())
+    assert np.mean(it == o.iters()) > 0.99
     d = lat.diagnostics(0)
     _say(f"    diag {d}")
 
@@ -107,12 +116,9 @@ def test_series_starter_same_alpha_fewer_iterations(elbm):
     compare(ser, 0, o, 1e-12)
     a0, i0 = plain.read_alpha(0)
     a1, i1 = ser.read_alpha(0)
-    both = (i0 >= 0) & (i1 >= 0)
-    err = np.abs(a1 - a0)[both] / a0[both]
+    check_alpha(a1, i1, a0, i0, label="alpha series vs plain")
     d0, d1 = plain.diagnostics(0), ser.diagnostics(0)
-    _say(f"    alpha series vs plain: q0.999 rel {np.quantile(err, 0.999):.2e} max {err.max():.2e}; mean Newton "
-         f"updates plain {d0['mean_newton_iters']:.3f} series {d1['mean_newton_iters']:.3f}")
-    assert np.quantile(err, 0.999) < 1e-9
+    _say(f"    mean updates plain {d0['mean_newton_iters']:.3f} series {d1['mean_newton_iters']:.3f}")
     assert d1["mean_newton_iters"] < 0.8 * d0["mean_newton_iters"]
 
 
@@ -174,17 +180,15 @@ def storage_rounding_error(params, box, steps):
             "phi": rel(emu.field(ora.F_PHI), ref.field(ora.F_PHI))}
 
 
-def check_fp32(lat, o, params, box, steps):
-    # Densities and potential: 1e-5 against the FP64 oracle.  Velocity: 1e-5,
-    # or 3x the error that FP32 storage of the populations alone produces in
-    # the oracle, whichever is larger (the entropic step amplifies storage
-    # rounding of the minority component's populations; no FP32 kernel can
-    # beat it).
-    errs = compare(lat, 0, o, 1e-5, fields=("rhoA", "rhoB", "phi"))
+def check_fp32(lat, o, params, box, steps, i=0):
+    # Densities, velocity and potential within 1e-5 of the FP64 oracle (field-
+    # max normalised).  The error that FP32 storage of the populations alone
+    # brings (the oracle with its populations rounded after every step) is
+    # reported beside it.
+    errs = compare(lat, i, o, 1e-5, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi"))
     store = storage_rounding_error(params, box, steps)
     _say("    FP32-storage-only oracle errors: " + " ".join(f"{k}={v:.2e}" for k, v in store.items()))
-    for k in ("ux", "uy", "uz"):
-        compare(lat, 0, o, max(1e-5, 3.0 * store[k]), fields=(k,))
+    return errs
 
 
 def test_efield_fp32_100_steps(elbm):
@@ -260,6 +264,39 @@ def test_jet_full_size_fp32(elbm):
     d = lat.diagnostics(0)
     _say(f"    diag: collisions {d['n_collisions']} fallbacks {d['n_fallback']} negative {d['n_negative']}")
     assert d["n_collisions"] > 0
+
+
+@pytest.mark.parametrize("guess", ["standard", "mlp"])
+def test_jet_reduced_fp32_100_steps(elbm, guess):
+    # The jet geometry with its full nozzle (radius 8, perturbed inlet disk,
+    # Poiseuille inflow 0.02, collector plane, electrodes, generator charge,
+    # Carreau n = 0.4) in a reduced 48x48x128 box, FP32 populations, 100 steps,
+    # with plain Newton from 2 and with the learned starter (the stored
+    # network): every field within the FP32 bar of the FP64 oracle.
+    import oracle as ora
+    from paper_1612_05404_amd import learned
+    wl = inputs.jet(nx=48, ny=48, nz=128, r_noz=8.0)
+    b = wl.boxes[0]
+    _say(f"[gpu parity] jet {b.nx}x{b.ny}x{b.nz} nozzle r 8, f32, 100 steps, starter {guess}")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess=guess)
+    if guess == "mlp":
+        lat.mlp_set_weights(learned.load_weights())
+    lat.step(100, record=True)
+    lat.sync()
+    o = ora.Oracle(wl.params, b, nthreads=NTHREADS)
+    o.step(100)
+    compare(lat, 0, o, 1e-5, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi"))
+    compare(lat, 0, o, 1e-4, fields=("q",))
+    al, it = lat.read_alpha(0)
+    oal, oit = o.field(ora.F_ALPHA), o.iters()
+    fluid = (b.node_type & 3) == inputs.FLUID
+    both = (it >= 0) & (oit >= 0) & fluid[None]
+    err = np.abs(al - oal)[both] / oal[both]
+    _say(f"    alpha vs oracle (FP32 populations on the GPU): max rel {err.max():.2e}")
+    d = lat.diagnostics(0)
+    _say(f"    diag: collisions {d['n_collisions']} fallbacks {d['n_fallback']} negative {d['n_negative']} "
+         f"mean updates {d['mean_newton_iters']:.4f}")
+    lat.close()
 
 
 def test_conservation_and_checkpoint(elbm):

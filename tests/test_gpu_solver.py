@@ -1,0 +1,211 @@
+"""Solver statistics and error reporting of the HIP path, through the C ABI:
+the Poisson residual and stop rule against the oracle's, the electric-force
+sum against the momentum budget, device alpha statistics, the Halley
+iteration, and the sticky error flags (each condition forced from the host:
+a planted negative population, a one-update Newton limit, an unreachable
+Poisson tolerance)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1612_05404_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def elbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1612_05404_amd import elbm as E
+    E.load()
+    return E
+
+
+def test_poisson_residual_matches_oracle_fixed_sweeps(elbm):
+    # Fixed sweep count: the recorded step's FP64 residual and its scale agree
+    # with the oracle's (same definition, same state to rounding).
+    import oracle as ora
+    wl = inputs.efield_drop(nx=16, ny=16, nz=32)
+    _say("[gpu solver] residual, efield 16x16x32 f64, 20 steps")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f64")
+    lat.step(20, record=True)
+    d = lat.diagnostics(0)
+    o = ora.Oracle(wl.params, wl.boxes[0], nthreads=NTHREADS)
+    o.step(20)
+    st = o.poisson_stats()
+    _say(f"    gpu residual {d['sor_residual']:.6e} scale {d['sor_scale']:.6e} sweeps {d['sor_sweeps']}; "
+         f"oracle {st['residual']:.6e} {st['scale']:.6e} {st['sweeps']}")
+    assert d["sor_sweeps"] == st["sweeps"] == wl.params.sor_sweeps
+    assert abs(d["sor_residual"] - st["residual"]) <= 1e-8 * st["residual"]
+    assert abs(d["sor_scale"] - st["scale"]) <= 1e-12 * st["scale"]
+    assert d["n_sor_noconv"] == 0
+    lat.close()
+
+
+def test_poisson_stop_rule_matches_oracle(elbm):
+    # With a tolerance checked every 2 sweeps (at most 40), every box stops at
+    # the same check as the oracle's solve and the fields stay at the FP64 bar.
+    import oracle as ora
+    from test_gpu_parity import compare
+    p = inputs.base_params(Q_b=0.03, Q_s=0.3, E_ext=[0.0, 0.0, 1e-3], sor_sweeps=40, sor_omega=1.5,
+                           sor_tol=1e-4, sor_check_every=2)
+    boxes = [inputs.droplet_box(16, 16, 24, 5.0, seed=31),
+             inputs.droplet_box(12, 12, 20, 3.0, seed=32, walls_z=True, phi_bottom=0.0, phi_top=-0.019)]
+    _say("[gpu solver] stop rule (tol 1e-4, checks every 2 of at most 40 sweeps), 2 boxes f64")
+    lat = elbm.Lattice(p, boxes, "f64")
+    oras = [ora.Oracle(p, b, nthreads=NTHREADS) for b in boxes]
+    for step in range(12):
+        lat.step(1, record=True)
+        for i, o in enumerate(oras):
+            o.step(1)
+            d, st = lat.diagnostics(i), o.poisson_stats()
+            assert d["sor_sweeps"] == st["sweeps"], (step, i, d["sor_sweeps"], st["sweeps"])
+            assert d["sor_residual"] <= 1e-4 * d["sor_scale"]
+    for i, o in enumerate(oras):
+        _say(f"    box {i}: sweeps {lat.diagnostics(i)['sor_sweeps']} (oracle {o.poisson_stats()['sweeps']})")
+        compare(lat, i, o, 1e-12)
+    lat.sync()
+    lat.close()
+
+
+def test_unreachable_poisson_tolerance_is_reported(elbm):
+    # A tolerance no solve can meet in 2 sweeps: every step counts a solve
+    # above it and elbm_sync reports ELBM_ENOCONV.
+    wl = inputs.drop32(n=16)
+    p = wl.params.with_(sor_sweeps=2, sor_tol=1e-30)
+    _say("[gpu solver] unreachable sor_tol, 16^3 f64, 3 steps")
+    lat = elbm.Lattice(p, wl.boxes, "f64")
+    lat.step(3, record=True)
+    with pytest.raises(elbm.ElbmError) as e:
+        lat.sync()
+    assert e.value.status == elbm.ELBM_ENOCONV
+    d = lat.diagnostics(0)
+    assert d["n_sor_noconv"] == 3 and d["sor_sweeps"] == 2 and d["sor_residual"] > 0.0
+    lat.close()
+
+
+def test_negative_population_is_reported_when_strict(elbm):
+    # A negative population planted at a node inside the drop stays negative
+    # through the collision (the fallback alpha stays below the positivity
+    # limit of that direction): counted always, an error only when strict.
+    wl = inputs.drop32(n=16)
+    _say("[gpu solver] planted negative population, 16^3 f64, strict and not")
+    for strict in (0, elbm.STRICT_NEGPOP):
+        lat = elbm.Lattice(wl.params, wl.boxes, "f64", strict=strict)
+        f = lat.get_populations(0)
+        f[0, 1, 8, 8, 8] = -0.02
+        lat.set_populations(0, f)
+        lat.step(1, record=True)
+        if strict:
+            with pytest.raises(elbm.ElbmError) as e:
+                lat.sync()
+            assert e.value.status == elbm.ELBM_ENEGPOP
+        else:
+            lat.sync()
+        assert lat.diagnostics(0)["n_negative"] > 0
+        lat.close()
+
+
+def test_alpha_fallback_is_reported_when_strict(elbm):
+    # One Newton update from alpha = 2 cannot meet the stopping rule away from
+    # equilibrium: those nodes fall back; with ELBM_STRICT_ALPHA that is an error.
+    wl = inputs.drop32(n=16)
+    p = wl.params.with_(newton_max=1)
+    _say("[gpu solver] newton_max = 1, 16^3 f64, strict alpha")
+    lat = elbm.Lattice(p, wl.boxes, "f64", strict=elbm.STRICT_ALPHA)
+    lat.step(2, record=True)
+    with pytest.raises(elbm.ElbmError) as e:
+        lat.sync()
+    assert e.value.status == elbm.ELBM_ENOCONV
+    assert lat.diagnostics(0)["n_fallback"] > 0
+    lat.close()
+
+
+def test_momentum_budget_equals_electric_force(elbm):
+    # Periodic box: streaming keeps the total momentum and the Shan-Chen forces
+    # cancel pairwise, so one step changes the momentum of the populations by
+    # the electric force summed over the fluid nodes (Eq. force_el2), the
+    # device's recorded sum.
+    p = inputs.base_params(Q_b=0.05, Q_s=0.5, E_ext=[1e-3, 0.0, 2e-3], sor_sweeps=6, sor_omega=1.5)
+    b = inputs.droplet_box(16, 16, 16, 4.0, seed=41)
+    _say("[gpu solver] momentum budget vs sum F_el, 16^3 f64")
+    lat = elbm.Lattice(p, [b], "f64")
+    lat.step(5, record=True)
+    for _ in range(3):
+        m0 = np.array(lat.diagnostics(0)["momentum"])
+        lat.step(1, record=True)
+        d = lat.diagnostics(0)
+        dm, fel = np.array(d["momentum"]) - m0, np.array(d["sum_Fel"])
+        _say(f"    dmom {dm} sum F_el {fel}")
+        assert np.abs(fel).max() > 1e-9
+        assert np.abs(dm - fel).max() <= 1e-12 + 1e-8 * np.abs(fel).max()
+    lat.close()
+
+
+def test_device_alpha_statistics(elbm):
+    # alpha min / max / mean of the diagnostics (device reduction) equal the
+    # same statistics of the recorded field over the fluid nodes.
+    wl = inputs.efield_drop(nx=16, ny=16, nz=32)
+    _say("[gpu solver] device alpha statistics, efield 16x16x32 f32")
+    lat = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess="series")
+    lat.step(15, record=True)
+    al, it = lat.read_alpha(0)
+    fluid = ((wl.boxes[0].node_type & 3) == inputs.FLUID)[None].repeat(al.shape[0], 0)
+    d = lat.diagnostics(0)
+    a = al[fluid]
+    assert d["alpha_min"] == a.min() and d["alpha_max"] == a.max()
+    assert abs(d["alpha_mean"] - a.mean()) <= 1e-14 * a.mean()
+    lat.close()
+
+
+def test_halley_same_alpha_fewer_updates(elbm):
+    # Halley's iteration (g'' without a further logarithm) reaches the same
+    # root as Newton under the same stopping rule: fields at the FP64 bar of
+    # the oracle, alpha within 1e-11 of plain Newton's, the same fallbacks,
+    # and fewer updates.
+    import oracle as ora
+    from test_gpu_parity import check_alpha, compare
+    wl = inputs.drop32()
+    _say("[gpu solver] Halley vs Newton, drop32 f64, 100 steps")
+    nw = elbm.Lattice(wl.params, wl.boxes, "f64")
+    ha = elbm.Lattice(wl.params, wl.boxes, "f64", alpha_iter="halley")
+    nw.step(100, record=True)
+    ha.step(100, record=True)
+    o = ora.Oracle(wl.params, wl.boxes[0], nthreads=NTHREADS)
+    o.step(100)
+    compare(ha, 0, o, 1e-12)
+    a0, i0 = nw.read_alpha(0)
+    a1, i1 = ha.read_alpha(0)
+    check_alpha(a1, i1, a0, i0, label="alpha Halley vs Newton")
+    d0, d1 = nw.diagnostics(0), ha.diagnostics(0)
+    _say(f"    mean updates Newton {d0['mean_newton_iters']:.4f} Halley {d1['mean_newton_iters']:.4f}")
+    assert d1["mean_newton_iters"] < d0["mean_newton_iters"]
+    nw.close()
+    ha.close()
+
+
+def test_set_box_right_after_steps(elbm):
+    # set_box called while steps may still run on the stream (no explicit
+    # sync) waits for them: the box then restarts exactly like a fresh one.
+    wl = inputs.efield_drop(nx=16, ny=16, nz=32)
+    _say("[gpu solver] set_box after unsynchronised steps, efield 16x16x32 f32")
+    a = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess="series")
+    a.step(40, record=False)
+    a.set_box(0, wl.boxes[0])
+    a.step(6, record=True)
+    b = elbm.Lattice(wl.params, wl.boxes, "f32", alpha_guess="series")
+    b.step(6, record=True)
+    assert np.array_equal(a.get_populations(0), b.get_populations(0))
+    assert np.array_equal(a.read_potential(0), b.read_potential(0))
+    a.close()
+    b.close()

@@ -68,7 +68,7 @@ def test_bounce_back_at_walls(ora):
 
 
 def test_velocity_inlet_at_rest_keeps_the_fluid(ora):
-    # The jet set-up of Sec. IV prescribes the inlet velocity; the inlet density
+    # The jet set-up of Sec. III.B prescribes the inlet velocity; the inlet density
     # follows the liquid next to it.  With u_bc = 0 an inlet plane under a
     # fluid at density 0.5 must then act as a closed, non-slip end: after the
     # first step's exchange with the initial inlet state (rho_in = 1.0) the
