@@ -1,27 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the coupled per-step update on one MI355X.
 
-Default workload: a charged drop between two fixed-potential electrodes
-(64 x 64 x 128 nodes, two Shan-Chen components, uniform E_z = 1e-3, Carreau
-fluid, FP32 populations and fields, FP64 entropic alpha, 8 red-black SOR
-sweeps of the Poisson equation every step).  One step = every stage of the
-update (pull, densities, curvature and charge, Poisson, electric field,
+Headline workload: the electrified jet, 128 x 128 x 512 nodes (8.4 M), two
+Shan-Chen components injected through a nozzle of radius 8 (1 % azimuthal
+perturbation, Poiseuille inflow 0.02) towards a collector plane held at a
+potential difference giving a mean E_z = 2e-3, generator-connected charge,
+Carreau fluid (n = 0.4), FP32 populations, FP64 entropic alpha, 8 red-black
+SOR sweeps of the Poisson equation every step.  One step = every stage of
+the update (pull, densities, curvature and charge, Poisson, electric field,
 forces, alpha, Carreau, collision) over the whole box.
 
-Prints one JSON line: MLUPS (million lattice-node updates per second) over K
-steps (default 2000, the whole configured run, after W warm-up steps from the
-initial state) replayed as captured step graphs, in the launch mapping the
-autotuner chose on a separate instance; the per-phase breakdown of the same
-W + K steps from HIP events on the library's stream (second instance, phases
-in order on one stream); the rooflines of the two collision kernels from their
-event-timed launches over steps 251..266, the window their hardware counters
-are taken on (third instance): k_alpha, the dominant one, bound by FP64
-arithmetic (its HBM roofline beside it), and k_collide against HBM; and the
-CPU oracle timed on a bounded sample.
+The jet is first formed: `--form` steps (default 10000, the configured run
+length) from the initial state, then checkpointed (populations and
+potential).  Each alpha starter (series root, learned network, plain Newton
+from 2) restarts from that checkpoint: one recorded step gives its alpha on
+the checkpoint state (compared with plain Newton's), the autotuner picks the
+launch mapping, then W warm-up steps and K timed steps replayed as captured
+step graphs (wall clock between device synchronisations).  `value` is the
+series starter's MLUPS; the learned and plain ones sit beside it.  A further
+instance times every phase of the same window with HIP events (phases in
+order on one stream): the per-kernel rooflines come from those times.
+
+Also reported: the batched ensemble (256 boxes, learned starter), and the
+CPU oracle timed on a bounded sample on the host.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,20 +37,7 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS coupled step, % of HBM roofline; learned-α vs plain Newton, same accuracy"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 COPY_MIB = 256
-ROOF_AT, ROOF_STEPS = 250, 16  # the roofline window: steps 251..266
-
-# Counted with rocprofv3 --pmc on the default workload with the series
-# starter and the autotuner's mapping, over the launches of steps 251..266
-# (early steps need more Newton updates): FP64 operations per node of one
-# k_alpha launch (64 lanes x (2 FMA + ADD + MUL + TRANS) wave instructions),
-# and the HBM bytes of one launch of each kernel (FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives for the same
-# counters).  None: not counted for the current kernels.
-ALPHA_FP64_FLOP_PER_NODE = 10954
-ALPHA_TRAFFIC_BYTES = 377_100_296
-COLLIDE_TRAFFIC_BYTES = 216_229_999
 
 
 def alpha_bytes_per_node(storage_bytes: int, ncomp: int) -> int:
@@ -64,30 +57,58 @@ def collide_bytes_per_node(storage_bytes: int, field_bytes: int, ncomp: int) -> 
     return pops + ncomp * 8 + fields + 1
 
 
-def step_bytes_per_node(storage_bytes: int, ncomp: int, sor_sweeps: int) -> int:
+def step_bytes_per_node(storage_bytes: int, ncomp: int, sor_sweeps: float) -> float:
     """Algorithmic bytes of a whole step per node: one read and one write of
     every population, the density/charge/potential fields materialised once
     (10 scalar fields written or read), 4 scalar fields per SOR sweep."""
     return 2 * ncomp * 19 * storage_bytes + 10 * storage_bytes + 4 * storage_bytes * sor_sweeps
 
 
-def cpu_baseline(wl, budget_s: float = 15.0, max_steps: int = 200):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inputs, budget_s: float = 12.0):
+    """The FP64 oracle on the host: all threads on the headline jet (whole
+    steps from its initial state, within the budget), one thread on the same
+    jet geometry reduced to 48 x 48 x 128 (the full box takes tens of seconds
+    per step on one thread)."""
     import oracle
     oracle.build(force=False)
-    box = wl.boxes[0]
-    o = oracle.Oracle(wl.params, box, nthreads=0)
-    threads = oracle.lib().ora_threads()
-    t0 = time.perf_counter()
-    n = 0
-    while n < max_steps:
-        o.step(1)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": box.n * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} steps of the same {box.nx}x{box.ny}x{box.nz} box, FP64 oracle, "
-                      f"{threads} OpenMP threads, {dt:.1f} s"}
+
+    def run(wl, nthreads, budget, max_steps=50):
+        o = oracle.Oracle(wl.params, wl.boxes[0], nthreads=nthreads)
+        used = oracle.lib().ora_threads()
+        t0 = time.perf_counter()
+        n = 0
+        while n < max_steps:
+            o.step(1)
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        dt = time.perf_counter() - t0
+        del o
+        return wl.nodes * n / dt / 1e6, n, dt, used
+
+    full = inputs.jet()
+    v, n, dt, used = run(full, 0, budget_s)
+    small = inputs.jet(nx=48, ny=48, nz=128, r_noz=8.0)
+    v1, n1, dt1, _ = run(small, 1, 0.5 * budget_s)
+    b = full.boxes[0]
+    return {"value": round(v, 4), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"{n} steps of the {b.nx}x{b.ny}x{b.nz} jet from its initial state, FP64 oracle, "
+                      f"{used} OpenMP threads, {dt:.1f} s",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": round(v1, 4), "unit": "MLUPS",
+                              "sample": f"{n1} steps of the jet geometry reduced to 48x48x128, 1 thread, "
+                                        f"{dt1:.1f} s"}}
 
 
 def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
@@ -119,93 +140,57 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
     nfb = sum(d["n_fallback"] for d in diags)
     lat.close()
     edges = sorted({b.nx for b in wl.boxes})
+    mlups = wl.nodes * steps / dt / 1e6
+    sb = step_bytes_per_node(4, wl.params.ncomp, wl.params.sor_sweeps)
     return {
         "workload": f"ensemble: {len(wl.boxes)} periodic drop boxes, edges {edges}, FP32 populations, FP64 alpha",
         "nodes": wl.nodes,
         "steps": steps,
-        "mlups": round(wl.nodes * steps / dt / 1e6, 3),
+        "mlups": round(mlups, 3),
         "ms_per_step": round(dt / steps * 1e3, 4),
+        "hbm_frac": round(sb * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
         "alpha_guess": mode,
         "mean_newton_iters": round(iters / max(ncol - nfb, 1), 4),
         "autotune": {"best": best, "ms_per_step": dict(
             [(f"tile{t}", round(float(ms[t]), 4)) for t in range(4)]
             + [(f"remap{r}", round(float(ms[4 + r]), 4)) for r in range(2)]
-            + [(f"graph{g}", round(float(ms[6 + k]), 4)) for k, g in enumerate((2, 4, 8))])},
+            + [(f"prio{r}", round(float(ms[6 + r]), 4)) for r in range(2)]
+            + [(f"graph{g}", round(float(ms[8 + k]), 4)) for k, g in enumerate((2, 4, 8))])},
     }
 
 
-def jet_leg(elbm, inputs, learned, warmup: int, steps: int):
-    """The jet (128x128x512, FP32, inlet disk and collector, Carreau, generator
-    charge): after `warmup` steps and the autotuner, `steps` graph-replayed
-    steps with each starter; MLUPS and mean Newton updates at identical alpha."""
-    import torch
-    t0 = time.perf_counter()
-    wl = inputs.jet()
-    b = wl.boxes[0]
-    print(f"[bench] jet {b.nx}x{b.ny}x{b.nz} (inputs {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    out = {"workload": f"jet: {b.nx}x{b.ny}x{b.nz}, inlet disk r 8, E_z 2e-3, Carreau n 0.4, FP32 populations, "
-                       f"FP64 alpha, {wl.params.sor_sweeps} SOR sweeps/step",
-           "nodes": wl.nodes, "warmup": warmup, "steps": steps, "starters": {}}
-    for mode in ("standard", "series", "mlp"):
-        if mode == "mlp" and not os.path.exists(learned.WEIGHTS):
-            continue
-        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
-        if mode == "mlp":
-            lat.mlp_set_weights(learned.load_weights())
-        lat.step(warmup, record=False)
-        launch, _ = lat.autotune(16)
-        lat.sync()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        lat.step(steps, record=False)
-        lat.sync()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        lat.step(1, record=True)
-        d = lat.diagnostics(0)
-        out["starters"][mode] = {"mlups": round(wl.nodes * steps / dt / 1e6, 3),
-                                 "mean_newton_iters": round(d["mean_newton_iters"], 4),
-                                 "fallback_frac": round(d["n_fallback"] / max(d["n_collisions"], 1), 6),
-                                 "launch": launch}
-        lat.close()
-        del lat
-        torch.cuda.empty_cache()
-    return out
+def parse_launch(text):
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (3, 4):
+        sys.exit(f"--launch takes remap,graph_steps,tile[,sweep_priority], got {text!r}")
+    return {"xcd_remap": v[0], "graph_steps": v[1], "tile": v[2], "sweep_priority": v[3] if len(v) == 4 else 0}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000,
-                    help="timed steps (default: the field drop's configured run length)")
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="efield_drop", choices=["efield_drop", "jet", "drop32", "ensemble"],
-                    help="ensemble only with --roofline-only (the default run times it in its own leg)")
+    ap.add_argument("--steps", type=int, default=500, help="timed steps after the warm-up (default 500)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps after the checkpoint and the autotuner")
+    ap.add_argument("--form", type=int, default=10000,
+                    help="steps that form the jet before the checkpoint (default 10000, the configured run)")
+    ap.add_argument("--starters", default="series,mlp,standard",
+                    help="alpha starters to time (the first is the reported value)")
+    ap.add_argument("--launch", default=None,
+                    help="launch mapping remap,graph_steps,tile[,sweep_priority] for every starter (no autotuner)")
+    ap.add_argument("--phase-steps", type=int, default=50, help="steps of the per-phase event timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--alpha-guess", default="series", choices=["series", "standard", "mlp"],
-                    help="initial guess of the alpha Newton iteration for the reported value")
-    ap.add_argument("--single-mode", action="store_true",
-                    help="time only the reported guess (no comparison run)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--ensemble-steps", type=int, default=100)
-    ap.add_argument("--no-jet", action="store_true", help="skip the jet leg (three starters)")
-    ap.add_argument("--jet-warmup", type=int, default=200)
-    ap.add_argument("--jet-steps", type=int, default=100)
-    ap.add_argument("--launch", default=None,
-                    help="launch mapping remap,graph_steps,tile[,sweep_priority] (skips the autotuner)")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="only the collision's roofline window (for counter runs)")
     args = ap.parse_args()
-    if args.workload == "ensemble" and not args.roofline_only:
-        ap.error("--workload ensemble serves --roofline-only counter runs; the default run times the ensemble itself")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
               f"the update has no multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
-    from paper_1612_05404_amd import elbm, inputs
+    from paper_1612_05404_amd import elbm, inputs, learned
 
     # A plain device copy of known size (read + write of COPY_MIB each): the
     # reference that scales HBM traffic counters taken over this program.
@@ -215,16 +200,17 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
-    wl = inputs.WORKLOADS[args.workload]()
+    t0 = time.perf_counter()
+    wl = inputs.jet()
     box = wl.boxes[0]
     nodes = wl.nodes
-    esz = 8 if wl.dtype == "f64" else 4
-    from paper_1612_05404_amd import learned
     have_net = os.path.exists(learned.WEIGHTS)
-    if args.alpha_guess == "mlp" and not have_net:
-        sys.exit(f"--alpha-guess mlp needs the stored network {learned.WEIGHTS}")
-    modes = [args.alpha_guess] + [m for m in ("standard", "series", "mlp")
-                                  if m != args.alpha_guess and (m != "mlp" or have_net)]
+    starters = [m for m in args.starters.split(",") if m and (m != "mlp" or have_net)]
+    if not starters:
+        sys.exit("no alpha starter to time")
+    print(f"[bench] jet {box.nx}x{box.ny}x{box.nz} (inputs {time.perf_counter() - t0:.1f} s), forming "
+          f"{args.form} steps", file=sys.stderr, flush=True)
+
     def make(mode, launch=None):
         lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
         if mode == "mlp":
@@ -233,92 +219,119 @@ def main():
             lat.set_launch(**launch)
         return lat
 
-    def tuned_launch(mode):
-        if args.launch:
-            v = [int(x) for x in args.launch.split(",")]
-            if len(v) not in (3, 4):
-                sys.exit(f"--launch takes remap,graph_steps,tile[,sweep_priority], got {args.launch!r}")
-            return {"xcd_remap": v[0], "graph_steps": v[1], "tile": v[2], "sweep_priority": v[3] if len(v) == 4 else 0}
-        # tuned on a throw-away instance: the timed runs start from the initial state
-        lat = make(mode)
-        lat.step(args.warmup, record=False)
-        launch, _ = lat.autotune(32)
-        lat.close()
-        return launch
+    # ---- formation run and checkpoint (series starter: the converged state
+    # does not depend on the starter)
+    t1 = time.perf_counter()
+    lat = make("series")
+    lat.step(args.form, record=True)
+    lat.sync()
+    f_ck = lat.get_populations(0)
+    phi_ck = lat.read_potential(0)
+    rho_ck, _ = lat.read_moments(0)
+    form_diag = lat.diagnostics(0)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    liquid = int((rho_ck[0] > wl.params.rho_th).sum())
+    print(f"[bench] formed in {time.perf_counter() - t1:.1f} s: {liquid} liquid nodes", file=sys.stderr, flush=True)
 
-    def roofline_window(mode, launch):
-        # k_alpha and k_collide times over the window where the counters are taken
+    def restore(mode, launch=None):
         lat = make(mode, launch)
-        lat.step(ROOF_AT, record=False)
-        lat.set_timing(True)
-        lat.step(ROOF_STEPS, record=False)
-        ph = lat.timing()
-        lat.close()
-        n = max(ph["steps"], 1)
-        return ph["alpha"] / n, ph["collide"] / n
+        lat.set_populations(0, f_ck)
+        lat.set_potential(0, phi_ck)
+        return lat
 
-    if args.roofline_only:
-        launch = tuned_launch(args.alpha_guess)
-        ams, cms = roofline_window(args.alpha_guess, launch)
-        print(json.dumps({"roofline_window": {"steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS], "alpha_ms": round(ams, 5),
-                                              "collide_ms": round(cms, 5), "launch": launch}}), flush=True)
-        return
-
-    results = {}
-    for mode in modes:
-        print(f"[bench] workload {wl.name} {box.nx}x{box.ny}x{box.nz} dtype {wl.dtype} sor_sweeps "
-              f"{wl.params.sor_sweeps} alpha guess {mode}", file=sys.stderr, flush=True)
-        launch = tuned_launch(mode)
-        # timed region: W warm-up steps, then K steps as replayed step graphs,
-        # wall clock between device-wide synchronisations
-        lat = make(mode, launch)
+    results, alphas = {}, {}
+    ref_mode = "standard"
+    for mode in starters + ([ref_mode] if ref_mode not in starters else []):
+        timed = mode in starters
+        print(f"[bench] starter {mode}", file=sys.stderr, flush=True)
+        lat = restore(mode)
+        lat.step(1, record=True)                 # alpha of every node on the checkpoint state
+        al, it = lat.read_alpha(0)
+        alphas[mode] = (al, it)
+        if not timed:
+            lat.close()
+            continue
+        launch = parse_launch(args.launch) if args.launch else None
+        if launch:
+            lat.set_launch(**launch)
+        else:
+            launch, _ = lat.autotune(16)
         lat.step(args.warmup, record=False)
+        d0 = lat.diagnostics(0)
         lat.sync()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ta = time.perf_counter()
         lat.step(args.steps, record=False)
         lat.sync()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        # one recorded step for the solver statistics (outside the timed region)
-        lat.step(1, record=True)
-        diag = lat.diagnostics(0)
+        tb = time.perf_counter()
+        lat.step(1, record=True)                 # solver statistics (outside the timed region)
+        d1 = lat.diagnostics(0)
         lat.close()
-        res = dict(dt=t1 - t0, diag=diag, launch=launch)
-        if mode == args.alpha_guess:
-            # the same W + K steps again with HIP events around every phase
-            # (direct launches): the per-phase breakdown of the timed run
-            lat = make(mode, launch)
-            lat.step(args.warmup, record=False)
-            lat.set_timing(True)
-            lat.step(args.steps, record=False)
-            res["ph"] = lat.timing()
-            lat.close()
-            res["roof_ms"] = roofline_window(mode, launch)
-        results[mode] = res
+        del lat
         torch.cuda.empty_cache()
-        if args.single_mode:
-            break
-    r = results[args.alpha_guess]
-    dt, ph, diag = r["dt"], r["ph"], r["diag"]
-    mlups = nodes * args.steps / dt / 1e6
-    steps_timed = max(ph["steps"], 1)
-    al_ms, co_ms = r["roof_ms"]
-    fesz = 4 if wl.dtype == "f32all" else 8
-    ab_ = alpha_bytes_per_node(esz, wl.params.ncomp)
-    cb = collide_bytes_per_node(esz, fesz, wl.params.ncomp)
-    al_gbs = ab_ * nodes / (al_ms * 1e-3) / 1e9
-    co_gbs = cb * nodes / (co_ms * 1e-3) / 1e9
-    counted = wl.name == "efield_drop" and args.alpha_guess == "series"
-    flop = ALPHA_FP64_FLOP_PER_NODE if counted else None
-    tflops = flop * nodes / (al_ms * 1e-3) / 1e12 if flop else None
+        ncol = d1["n_collisions"] - d0["n_collisions"]
+        nfb = d1["n_fallback"] - d0["n_fallback"]
+        results[mode] = dict(dt=tb - ta, launch=launch, d1=d1, ncol=ncol, nfb=nfb,
+                             neg=d1["n_negative"] - d0["n_negative"])
+
+    # alpha of each starter against plain Newton on the checkpoint state
+    a_ref, i_ref = alphas[ref_mode]
+    fluid = ((box.node_type & 3) == inputs.FLUID)[None]
+    for mode, (al, it) in alphas.items():
+        if mode not in results:
+            continue
+        both = (it >= 0) & (i_ref >= 0) & fluid
+        err = np.abs(al - a_ref)[both] / a_ref[both]
+        results[mode]["alpha_err"] = float(err.max()) if err.size else 0.0
+        results[mode]["same_fallbacks"] = bool(np.array_equal(it < 0, i_ref < 0))
+        # mean updates of that one recorded step (the checkpoint state)
+        results[mode]["ck_iters"] = float(it[(it >= 0) & fluid].mean())
+    del alphas
+
+    # ---- per-phase device time of the same window (phases in order on one stream)
+    head = starters[0]
+    r = results[head]
+    lat = restore(head, r["launch"])
+    lat.step(1, record=False)
+    lat.set_timing(True)
+    lat.step(args.phase_steps, record=False)
+    ph = lat.timing()
+    lat.close()
+    del lat, f_ck
+    torch.cuda.empty_cache()
+    nph = max(ph["steps"], 1)
+    phase_ms = {k: v / nph for k, v in ph.items() if k != "steps"}
+
+    esz = 4
+    mlups = nodes * args.steps / r["dt"] / 1e6
+    ms_step = r["dt"] / args.steps * 1e3
     sb = step_bytes_per_node(esz, wl.params.ncomp, wl.params.sor_sweeps)
-    comparison = {
-        m: {"mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
-            "mean_newton_iters": round(v["diag"]["mean_newton_iters"], 4),
-            "launch": v["launch"]}
-        for m, v in results.items()
-    }
+    step_gbs = sb * nodes / (ms_step * 1e-3) / 1e9
+    ab_ = alpha_bytes_per_node(esz, wl.params.ncomp)
+    cb = collide_bytes_per_node(esz, 8, wl.params.ncomp)
+    kernels = {}
+    for k, nbytes in (("alpha", ab_), ("collide", cb)):
+        ms = phase_ms[k]
+        gbs = nbytes * nodes / (ms * 1e-3) / 1e9
+        kernels["k_" + k] = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": nbytes,
+                             "avg_ms": round(ms, 5)}
+    starters_out = {}
+    for mode, v in results.items():
+        starters_out[mode] = {
+            "mlups": round(nodes * args.steps / v["dt"] / 1e6, 3),
+            "ms_per_step": round(v["dt"] / args.steps * 1e3, 4),
+            "mean_newton_iters": round(v["d1"]["mean_newton_iters"], 4),
+            "checkpoint_step_updates": round(v["ck_iters"], 4),
+            "alpha_max_rel_err_vs_plain": v["alpha_err"],
+            "same_fallback_nodes_as_plain": v["same_fallbacks"],
+            "window_fallback_frac": round(v["nfb"] / max(v["ncol"], 1), 7),
+            "window_negative_pop_frac": round(v["neg"] / max(19 * v["ncol"], 1), 8),
+            "launch": v["launch"],
+        }
     out = {
         "metric": METRIC,
         "value": round(mlups, 3),
@@ -326,69 +339,49 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "ms_per_step": round(ms_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": wl.dtype,
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{wl.name}: {box.nx}x{box.ny}x{box.nz} two-component charged drop, "
-                        f"FP32 populations, FP64 alpha, Carreau, {wl.params.sor_sweeps} SOR sweeps/step"
-            if wl.name == "efield_drop" else f"{wl.name}: {box.nx}x{box.ny}x{box.nz}",
+            "workload": f"jet: {box.nx}x{box.ny}x{box.nz} charged leaky-dielectric jet, nozzle radius 8, "
+                        f"E_z 2e-3, Carreau n 0.4, generator charge, FP32 populations / FP64 fields, "
+                        f"FP64 alpha, {wl.params.sor_sweeps} SOR sweeps/step",
             "nodes": nodes,
+            "start_step": args.form + 1 + args.warmup,
+            "formed_steps": args.form,
+            "liquid_nodes_at_checkpoint": liquid,
             "sor_sweeps": wl.params.sor_sweeps,
-            "alpha_guess": args.alpha_guess,
+            "alpha_guess": head,
             "alpha_precision": "f64",
             "launch": r["launch"],
         },
         "roofline": {
-            "kernel": "k_alpha",
-            "bound": "alu",
-            "achieved": round(tflops, 3) if tflops else None,
-            "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(tflops / FP64_PEAK_TFLOPS, 4) if tflops else None,
-            "traffic": ALPHA_TRAFFIC_BYTES if counted else None,
-            "fp64_flop_per_node": flop,
-            "avg_ms": round(al_ms, 5),
-            "window_steps": [ROOF_AT + 1, ROOF_AT + ROOF_STEPS],
-        },
-        "roofline_hbm": {
-            "kernel": "k_alpha",
+            "kernel": "coupled step (all kernels of one step)",
             "bound": "hbm",
-            "achieved": round(al_gbs, 2),
+            "achieved": round(step_gbs, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(al_gbs / HBM_PEAK_GBS, 4),
-            "traffic": ALPHA_TRAFFIC_BYTES if counted else None,
-            "bytes_per_node": ab_,
-            "avg_ms": round(al_ms, 5),
+            "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_node": sb,
+            "avg_ms": round(ms_step, 5),
         },
-        "roofline_collide": {
-            "kernel": "k_collide",
-            "bound": "hbm",
-            "achieved": round(co_gbs, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(co_gbs / HBM_PEAK_GBS, 4),
-            "traffic": COLLIDE_TRAFFIC_BYTES if counted else None,
-            "bytes_per_node": cb,
-            "avg_ms": round(co_ms, 5),
-        },
-        "step_effective_gbs": round(sb * mlups * 1e6 / 1e9, 2),
-        "step_bytes_per_node": sb,
-        "phase_ms_per_step": {k: round(v / steps_timed, 5) for k, v in ph.items() if k != "steps"},
-        "mean_newton_iters": round(diag["mean_newton_iters"], 4),
-        "alpha_fallback_frac": round(diag["n_fallback"] / max(diag["n_collisions"], 1), 6),
-        "alpha_guess_comparison": comparison,
+        "roofline_kernels": kernels,
+        "phase_ms_per_step": {k: round(v, 5) for k, v in phase_ms.items()},
+        "phase_steps": args.phase_steps,
+        "starters": starters_out,
+        "formation": {"steps": args.form, "mean_newton_iters": round(form_diag["mean_newton_iters"], 4),
+                      "fallback_frac": round(form_diag["n_fallback"] / max(form_diag["n_collisions"], 1), 7),
+                      "sor_residual_rel": round(form_diag["sor_residual"] / max(form_diag["sor_scale"], 1e-300), 6)},
     }
-    if not args.no_ensemble and args.workload == "efield_drop":
+    if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32)
-    if not args.no_jet and args.workload == "efield_drop":
-        out["jet"] = jet_leg(elbm, inputs, learned, args.jet_warmup, args.jet_steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inputs)
     print(json.dumps(out), flush=True)
 
 

@@ -43,7 +43,8 @@ struct elbm_ctx {
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
   size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_nbm, o_reca,
-      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, total;
+      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, o_nlc, o_nli, o_nlL,
+      o_nlA, o_nlM, o_nla, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
@@ -167,6 +168,12 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.block_box = (const int32_t *)(b + c->o_bb);
   a.partials = (double *)(b + c->o_part);
   a.res_part = (double *)(b + c->o_rpart);
+  a.nl_count = (int32_t *)(b + c->o_nlc);
+  a.nl_idx = (uint32_t *)(b + c->o_nli);
+  a.nl_L = (double *)(b + c->o_nlL);
+  a.nl_amax = (double *)(b + c->o_nlA);
+  a.nl_M2 = (double *)(b + c->o_nlM);
+  a.nl_a = (double *)(b + c->o_nla);
   a.fel_part = (double *)(b + c->o_fpart);
   a.scal = (double *)(b + c->o_scal);
   a.cnt = (unsigned long long *)(b + c->o_cnt);
@@ -254,13 +261,18 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   mark(c, ev, 0);
   hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
   mark(c, ev, 1);
+  // the two alpha passes: screening over every node, then the iteration list
+  auto alpha_passes = [&]() {
+    hipLaunchKernelGGL((k_alpha<T, F, C>), dim3(cgrid.x, C), blk, 0, as, a, M, rec);
+    if (M.alpha_guess == ELBM_GUESS_MLP)
+      hipLaunchKernelGGL((k_alpha_newton<T, F, C, true>), dim3(NL_GRID), blk, 0, as, a, M, make_mlp(c), rec);
+    else
+      hipLaunchKernelGGL((k_alpha_newton<T, F, C, false>), dim3(NL_GRID), blk, 0, as, a, M, make_mlp(c), rec);
+  };
   if (fork) {
     HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-    if (M.alpha_guess == ELBM_GUESS_MLP)
-      hipLaunchKernelGGL((k_alpha<T, F, C, true>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
-    else
-      hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+    alpha_passes();
     HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   }
   hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
@@ -298,10 +310,7 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   if (fork) {
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   } else {
-    if (M.alpha_guess == ELBM_GUESS_MLP)
-      hipLaunchKernelGGL((k_alpha<T, F, C, true>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
-    else
-      hipLaunchKernelGGL((k_alpha<T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+    alpha_passes();
   }
   mark(c, ev, 5);
   hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
@@ -574,6 +583,12 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_scal = take(sizeof(double) * NSCAL * nboxes);
   c->o_cnt = take(sizeof(unsigned long long) * NCNT * nboxes);
   c->o_err = take(sizeof(uint32_t) * 4);
+  c->o_nlc = take(sizeof(int32_t) * 4);
+  c->o_nli = take(sizeof(uint32_t) * (size_t)C * N);
+  c->o_nlL = take(sizeof(double) * (size_t)C * N);
+  c->o_nlA = take(sizeof(double) * (size_t)C * N);
+  c->o_nlM = take(sizeof(double) * (size_t)C * N);
+  c->o_nla = take(sizeof(double) * (size_t)C * N);
   c->o_mp = take(sizeof(float) * MLP_NPARAM);
   c->o_mm = take(sizeof(float) * MLP_NPARAM);
   c->o_mv = take(sizeof(float) * MLP_NPARAM);

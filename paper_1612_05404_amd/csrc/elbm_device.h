@@ -72,6 +72,10 @@ struct Ptrs {
   const BoxDev *boxes;
   const int32_t *block_box;
   double *partials;     // [nblocks][4]
+  // node-components whose alpha needs the iteration (screening pass -> Newton pass)
+  int32_t *nl_count;    // entries this step (zeroed by k_density)
+  uint32_t *nl_idx;     // [C N] 2 g + s (one component: g)
+  double *nl_L, *nl_amax, *nl_M2, *nl_a;  // [C N] set-up values; nl_a < 0: learned starter wanted, start -nl_a
   double *res_part;     // [nblocks][2] Poisson residual and max|rhs| per block
   double *fel_part;     // [nblocks][3] electric force summed per block (recorded steps)
   double *scal;         // [nboxes][NSCAL]
@@ -281,6 +285,30 @@ __device__ __forceinline__ double log1p_fast(double y) {
   return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * q + c * __builtin_amdgcn_rcp(t)));
 }
 
+// ln(1 + y) for |y| <= 1/4 to ~2 ulp without the range reduction of
+// log1p_fast: ln(1 + y) = 2 atanh(s), s = y / (2 + y) with the rounding error
+// of 2 + y folded in (Fast2Sum, |y| < 2), |s| <= 1/7, summed as
+// 2 s sum_{k=0}^{9} s^2k / (2k + 1) (first dropped term below 1e-18 relative).
+__device__ __forceinline__ double log1p_small(double y) {
+  const double t = 2.0 + y;
+  const double e = (2.0 - t) + y;  // t + e = 2 + y exactly
+  const double r = rcp_nr(t);
+  const double s = (y * r) * fma(-e, r, 1.0);
+  const double s2 = s * s;
+  double q = 1.0 / 19.0;
+  q = fma(q, s2, 1.0 / 17.0);
+  q = fma(q, s2, 1.0 / 15.0);
+  q = fma(q, s2, 1.0 / 13.0);
+  q = fma(q, s2, 1.0 / 11.0);
+  q = fma(q, s2, 1.0 / 9.0);
+  q = fma(q, s2, 1.0 / 7.0);
+  q = fma(q, s2, 1.0 / 5.0);
+  q = fma(q, s2, 1.0 / 3.0);
+  q = fma(q, s2, 1.0);
+  return 2.0 * s * q;
+}
+constexpr double LOG1P_SMALL_MAX = 0.25;
+
 // e^x for |x| < 700 to ~2 ulp: x = k ln2 + r with the same split of ln2 as
 // log1p_fast (k ln2_hi exact), |r| <= ln2/2, e^r by its Taylor series through
 // r^13 (first dropped term below 3e-18 relative), then the power of two.
@@ -305,11 +333,33 @@ __device__ __forceinline__ double exp_fast(double x) {
 }
 
 // (1 + q)^e for q >= 0, the Carreau factor: e^(e ln(1 + q)) in FP64 (no
-// rounding of 1 + q), the library pow in FP32.
+// rounding of 1 + q), the library pow in FP32.  For q < 2^-10 (a shear rate
+// well below 1/lambda: most of a flow at rest) both factors are short
+// Taylor series: ln(1 + q) through q^6 and e^t, |t| = |e| q < 2e-3, through
+// t^6 (dropped terms below 2e-19 relative).
 template <typename R>
 __device__ __forceinline__ R pow1p(R q, R e) {
-  if constexpr (sizeof(R) == 8) return exp_fast(e * log1p_fast(q));
-  else return pow(R(1) + q, e);
+  if constexpr (sizeof(R) == 8) {
+    if (q < 0.0009765625) {
+      double l = -1.0 / 6.0;
+      l = fma(l, q, 1.0 / 5.0);
+      l = fma(l, q, -1.0 / 4.0);
+      l = fma(l, q, 1.0 / 3.0);
+      l = fma(l, q, -0.5);
+      l = fma(l, q, 1.0);
+      const double t = e * (l * q);
+      double x = 1.0 / 720.0;
+      x = fma(x, t, 1.0 / 120.0);
+      x = fma(x, t, 1.0 / 24.0);
+      x = fma(x, t, 1.0 / 6.0);
+      x = fma(x, t, 0.5);
+      x = fma(x, t, 1.0);
+      return fma(x, t, 1.0);
+    }
+    return exp_fast(e * log1p_fast(q));
+  } else {
+    return pow(R(1) + q, e);
+  }
 }
 
 // phi(y) = (1+y) ln(1+y) - y given l = ln(1+y), cancellation-free: Taylor
@@ -389,6 +439,22 @@ __device__ __forceinline__ double series_q(double b, double L, const double *M) 
 }
 __device__ __forceinline__ double series_dq(double b, const double *M) {
   constexpr int D = SERIES_DEG;
+  double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D);
+#pragma unroll
+  for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k));
+  return h;
+}
+
+// The same truncated series at any degree D (M[k - 2] = M_k, k <= D + 1).
+template <int D>
+__device__ __forceinline__ double series_qd(double b, double L, const double *M) {
+  double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D * (D - 1));
+#pragma unroll
+  for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k * (k - 1)));
+  return fma(b, h, L);
+}
+template <int D>
+__device__ __forceinline__ double series_dqd(double b, const double *M) {
   double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D);
 #pragma unroll
   for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k));
@@ -475,6 +541,115 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
   return st;
 }
 
+// The alpha set-up of one node and component from registers (the screening
+// pass of the collision's alpha): the same quantities and decisions as
+// alpha_setup, with x_p held in registers instead of LDS.  Two variants,
+// chosen per wave (every lane takes the same one): the quiet one, for waves
+// whose fluid lanes all have max|x| <= 2.5e-3 and max|y| <= 1/4 with
+// y_p = f_p/(w_p rho) - 1, forms L with log1p_small and the series at
+// degree 6 (there its tail bound still accepts at alpha near 2:
+// (2 max|x|)^5 / 21 < 2.5e-13); the other one with log1p_fast and degree
+// SERIES_DEG.  Either returns a root within the stopping rule.
+template <typename T, int D, bool QUIET>
+__device__ __forceinline__ AlphaSetup alpha_screen_tail(const T (&f)[NQ], const double *xs, double rho,
+                                                        double ux, double uy, double uz, double xmax, double amax,
+                                                        bool nonpos, int guess, double rtol) {
+  // the equilibria and y_p are recomputed here rather than kept from the
+  // first pass (38 + 38 registers): the empty asm hides that rho and u are
+  // the same values, so the compiler cannot carry them over
+  asm volatile("" : "+v"(rho), "+v"(ux), "+v"(uy), "+v"(uz));
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double irho = rcp_nr(rho);
+  double L = 0.0;
+  double M[D];  // M[k - 2] = M_k, k = 2 .. D + 1
+#pragma unroll
+  for (int k = 0; k < D; ++k) M[k] = 0.0;
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) {
+    const double fp = double(f[p]);
+    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
+    const double y = (fp - wgt(p) * rho) * (irho * (1.0 / wgt(p)));
+    L += d * (QUIET ? log1p_small(y) : log1p_fast(y));
+    const double x = xs[p * XSTRIDE];
+    double t = fp * x * x;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      M[k] += t;
+      t *= x;
+    }
+  }
+  AlphaSetup st;
+  st.M2 = M[0];
+  st.L = L;
+  st.amax = amax;
+  st.xmax = xmax;
+  st.a = 2.0;
+  st.want_learned = false;
+  if (nonpos) {
+    st.state = 2;
+    return st;
+  }
+  if (xmax < 1e-12) {
+    st.state = 1;
+    return st;
+  }
+  st.state = L < 0.0 ? 0 : 2;
+  if (st.state == 0 && (guess == ELBM_GUESS_SERIES || guess == ELBM_GUESS_MLP)) {
+    double b = 2.0;
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {
+      const double q = series_qd<D>(b, L, M);
+      const double dq = series_dqd<D>(b, M);
+      if (!(dq > 0.0)) break;
+      b -= q / dq;
+    }
+    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
+      st.a = b;
+      const double bx = b * xmax;
+      if (bx < 0.5) {
+        const double qb = series_qd<D>(b, L, M);
+        double bd = b;  // b^D
+#pragma unroll
+        for (int k = 1; k < D; ++k) bd *= b;
+        const double tail = bd * M[D - 1] / (double((D + 1) * D) * (1.0 - bx));
+        if (b * (fabs(qb) + tail) <= 0.25 * rtol * b * b * M[0] * (1.0 - bx / 3.0)) st.state = 3;
+      }
+    } else {
+      st.want_learned = guess == ELBM_GUESS_MLP;
+    }
+  }
+  return st;
+}
+
+constexpr double QUIET_XMAX = 2.5e-3;
+
+// fl: this lane holds a fluid node (the others take part in the wave-wide
+// choice only).  f: the 19 pulled populations; rho, u: their FP64 moments;
+// xs: the thread's LDS column for x_p (element p at p * XSTRIDE).
+template <typename T>
+__device__ __forceinline__ AlphaSetup alpha_screen(const T (&f)[NQ], double *xs, bool fl, double rho, double ux,
+                                                   double uy, double uz, int guess, double rtol) {
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double irho = rcp_nr(rho);
+  double xmax = 0.0, xmin = 0.0, ymax = 0.0;
+  bool nonpos = false;
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) {
+    const double fp = double(f[p]);
+    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
+    const double x = d * rcp_nr(fp);
+    xs[p * XSTRIDE] = x;
+    nonpos |= !(fp > 0.0);
+    xmax = fmax(xmax, fabs(x));
+    xmin = fmin(xmin, x);
+    ymax = fmax(ymax, fabs((fp - wgt(p) * rho) * (irho * (1.0 / wgt(p)))));
+  }
+  const double amax = xmin < 0.0 ? -rcp_nr(xmin) : INFINITY;
+  const bool quiet = !fl || (xmax <= QUIET_XMAX && ymax <= LOG1P_SMALL_MAX);
+  if (__all(quiet)) return alpha_screen_tail<T, 6, true>(f, xs, rho, ux, uy, uz, xmax, amax, nonpos, guess, rtol);
+  return alpha_screen_tail<T, SERIES_DEG, false>(f, xs, rho, ux, uy, uz, xmax, amax, nonpos, guess, rtol);
+}
+
 // Newton's starting point for a node that needs the iteration (state 0).
 __device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
   double a = st.a;
@@ -500,10 +675,13 @@ __device__ __forceinline__ double alpha_g_top(const T *f, const double *xs, doub
 // Newton (or Halley) on g from a inside (0, amax) (f, xs as for the set-up
 // pass).  The first step that would leave the interval at the top checks that
 // a root exists at all (alpha_g_top); none: the fallback at once.  Halley's
-// step a - 2 g g' / (2 g'^2 - g g'') uses g'' = sum_p f_p x_p^2 / (1 + a x_p)
-// (one reciprocal per direction, no logarithm); where its denominator is not
-// positive the Newton step is taken.  The Taylor bound that skips the final
-// evaluation holds for Newton steps only.
+// step a - (g / g') / (1 - h), h = g g'' / (2 g'^2), uses
+// g'' = sum_p f_p x_p^2 / (1 + a x_p) (one reciprocal per direction, no
+// logarithm); it is taken while |h| < 1/2 (at most twice the Newton step),
+// else the Newton step: next to a_max a nearly vanishing population makes
+// g'' large, h approaches 1 and the unguarded step leaves the interval and
+// cycles.  The Taylor bound that skips the final evaluation holds for
+// Newton steps only.
 template <typename T>
 __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double M2,
                                                 double a, double rtol, int maxit, int &iters, bool halley) {
@@ -530,9 +708,9 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
       double an = (gp > 0.0) ? a - g / gp : 2.0 * a;
       bool newton = gp > 0.0 && an > 0.0 && an < amax;
       if (halley && gp > 0.0) {
-        const double den = 2.0 * gp * gp - g * gpp;
-        if (den > 0.0) {
-          an = a - 2.0 * g * gp / den;
+        const double h = g * gpp / (2.0 * gp * gp);
+        if (fabs(h) < 0.5) {
+          an = a - (g / gp) / (1.0 - h);
           newton = false;
         }
       }

@@ -47,6 +47,7 @@ template <typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.nl_count = 0;  // this step's alpha iteration list
   if (!nd.live) return;
   const int k = a.type[nd.g] & 3;
   const uint32_t msk = a.nbm[nd.g];  // the source of p is the neighbour in direction opp(p)
@@ -428,64 +429,217 @@ __device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M,
   }
 }
 
-// The collision (Eq. lattice-b) in two kernels.  The entropic alpha (Eq.
+// The collision (Eq. lattice-b) in three kernels.  The entropic alpha (Eq.
 // entropic) and the Carreau viscosity depend only on the pulled populations,
-// not on the forces, so k_alpha needs nothing of the step's field chain
-// (densities, charge, Poisson, E) and runs beside it on a second stream; it
-// leaves alpha * beta per node and component.  k_collide then adds the forces
-// and writes the post-collision populations.
+// not on the forces, so the alpha kernels need nothing of the step's field
+// chain (densities, charge, Poisson, E) and run beside it on a second stream;
+// they leave alpha * beta per node and component.  k_collide then adds the
+// forces and writes the post-collision populations.
+//
+// k_alpha screens every node: its set-up (moments, x_p, L, the series root
+// and its bound) decides most nodes at once -- at equilibrium, a series root
+// the bound accepts, or no root (fallback) -- and it finishes those with the
+// viscosity.  The others (the iteration is needed) go on a device list, which
+// k_alpha_newton works through densely: full waves of nodes that iterate,
+// the learned starter's matrix-core inference on whole waves.
 
-// k_alpha: for each fluid node and component, pull the 19 populations and
-// their FP64 moments, (LEARN) run the learned starter over the wave, solve
-// alpha in FP64, evaluate the viscosity, store ab = alpha c_s^2/(2 nu + c_s^2).
-// Per-lane work is predicated on `fl` so that the matrix-core section runs on
-// whole waves.  With FP32 populations two blocks fit a CU's LDS: the register
-// budget is held to two waves per SIMD (matrix accumulators included).
+// Carreau viscosity (Eqs. strain2, carreau) of one component from the
+// components of its non-equilibrium stress Pi = sum_p (f_p - f_eq_p) c_p c_p,
+// in the field precision R; nu0 when the Carreau law is off.
+template <typename R>
+__device__ __forceinline__ double viscosity(const Model &M, double nflow, double P00, double P11, double P22,
+                                            double P01, double P02, double P12, double rho, double al) {
+  if (!M.carreau) return M.nu0;
+  const R Pn = sym3_norm2<R>(R(P00), R(P11), R(P22), R(P01), R(P02), R(P12));
+  const R nf = R(nflow);
+  const R gd = shear_rate<R>(Pn, R(rho), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
+  const R lg = R(M.lam) * gd;
+  return double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow1p<R>(lg * lg, R(0.5) * (nf - R(1))));
+}
+
+// Per-wave counters of the alpha kernels added to the boxes' counters: one
+// atomic per wave and counter when the wave's active lanes share a box.
+__device__ __forceinline__ void alpha_counters(unsigned long long *cnt, uint32_t *err, const Model &M, bool act,
+                                               int bb, unsigned long long c_fb, unsigned long long c_it,
+                                               unsigned long long c_col) {
+  const unsigned long long am = __ballot(act);
+  if (!am) return;
+  const int lane = threadIdx.x & 63;
+  const int first = __ffsll((long long)am) - 1;
+  const int bb0 = __shfl(bb, first, 64);
+  if (__all(!act || bb == bb0)) {
+    c_fb = wave_sum_u64(c_fb);
+    c_it = wave_sum_u64(c_it);
+    c_col = wave_sum_u64(c_col);
+    if (lane == first) {
+      unsigned long long *cn = cnt + (int64_t)bb0 * NCNT;
+      if (c_fb) atomicAdd(cn + 0, c_fb);
+      if (c_it) atomicAdd(cn + 1, c_it);
+      if (c_col) atomicAdd(cn + 4, c_col);
+      if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(err, ERR_ALPHA);
+    }
+  } else if (act) {
+    unsigned long long *cn = cnt + (int64_t)bb * NCNT;
+    if (c_fb) atomicAdd(cn + 0, c_fb);
+    if (c_it) atomicAdd(cn + 1, c_it);
+    if (c_col) atomicAdd(cn + 4, c_col);
+    if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(err, ERR_ALPHA);
+  }
+}
+
+// k_alpha (screening pass): one thread per fluid node and component (the
+// component is the grid's y index): the 19 pulled populations in registers,
+// their FP64 moments and the alpha set-up (alpha_screen).  Decided nodes get
+// alpha, the viscosity and alpha * beta; the rest are appended to the
+// iteration list (one atomic per wave).
+template <typename T, typename F, int C>
+__global__ __launch_bounds__(BLK, 2) void k_alpha(Ptrs<T, F> a, Model M, int record) {
+  __shared__ __align__(16) double lds_x[NQ * BLK];  // x_p per thread: column p * 64 + lane of its wave
+  Node nd;
+  if (a.tx) decode_tile(a, nd);
+  else decode(a, nd);
+  const int s = C == 2 ? (int)blockIdx.y : 0;
+  const int lane = threadIdx.x & 63;
+  unsigned long long c_fb = 0, c_col = 0;
+  const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
+  const bool fl = nd.live && k == K_FLUID;
+  const uint32_t solid = fl ? a.nbm[nd.g] : 0u;  // neighbour p solid or outside (bit p)
+  // ---- pulled populations and their moments, summed in FP64 whatever the
+  // storage: the equilibrium of the alpha solve must carry exactly the
+  // density and momentum of f (sum Delta = 0), or the rounding of an FP32
+  // sum swamps the O(|Delta|^2) entropy balance.
+  T f[NQ];
+  double dr = 1.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  if (fl) {
+    dr = 0.0;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) {
+      const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
+      const bool bounce = (p != 0) && ((solid >> q) & 1u);
+      const int m = p ? nbr(nd.B, nd.x, nd.y, nd.z, kCx[q], kCy[q], kCz[q]) : nd.n;
+      f[p] = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g] : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + m];
+      const double dv = double(f[p]);
+      dr += dv;
+      jx += double(kCx[p]) * dv;
+      jy += double(kCy[p]) * dv;
+      jz += double(kCz[p]) * dv;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) f[p] = T(wgt(p));
+  }
+  const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+  double *xs = lds_x + (threadIdx.x >> 6) * (NQ * 64) + lane;
+  const AlphaSetup st = alpha_screen<T>(f, xs, fl, dr, ux, uy, uz, M.alpha_guess, M.rtol);
+  const bool need = fl && st.state == 0;
+  if (fl && !need) {
+    const double al = st.state == 1 ? 2.0 : st.state == 3 ? st.a : fmin(2.0, 0.99 * st.amax);
+    const int its = st.state == 2 ? -1 : 0;
+    c_col = 1;
+    if (its < 0) c_fb = 1;
+    double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (M.carreau) {
+      // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
+      // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
+#pragma unroll
+      for (int p = 0; p < NQ; ++p) {
+        const double d = double(f[p]);
+        P[0] += d * double(kCx[p] * kCx[p]);
+        P[1] += d * double(kCy[p] * kCy[p]);
+        P[2] += d * double(kCz[p] * kCz[p]);
+        P[3] += d * double(kCx[p] * kCy[p]);
+        P[4] += d * double(kCx[p] * kCz[p]);
+        P[5] += d * double(kCy[p] * kCz[p]);
+      }
+      P[0] -= dr * (CS2 + ux * ux);
+      P[1] -= dr * (CS2 + uy * uy);
+      P[2] -= dr * (CS2 + uz * uz);
+      P[3] -= dr * (ux * uy);
+      P[4] -= dr * (ux * uz);
+      P[5] -= dr * (uy * uz);
+    }
+    const double nu = viscosity<F>(M, nd.B.n_flow, P[0], P[1], P[2], P[3], P[4], P[5], dr, al);
+    a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
+    if (record) {
+      a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
+      a.rec_iters[(int64_t)s * a.N + nd.g] = its;
+    }
+  } else if (nd.live && record && !fl) {
+    a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
+    a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
+  }
+  // ---- append the nodes that iterate: one atomic per wave
+  const unsigned long long bal = __ballot(need);
+  if (bal) {
+    const int first = __ffsll((long long)bal) - 1;
+    int base = 0;
+    if (lane == first) base = atomicAdd(a.nl_count, (int)__popcll(bal));
+    base = __shfl(base, first, 64);
+    if (need) {
+      const int i = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+      a.nl_idx[i] = (uint32_t)(C == 2 ? 2 * nd.g + s : nd.g);
+      a.nl_L[i] = st.L;
+      a.nl_amax[i] = st.amax;
+      a.nl_M2[i] = st.M2;
+      a.nl_a[i] = st.want_learned ? -st.a : st.a;
+    }
+  }
+  alpha_counters(a.cnt, a.err, M, nd.live, nd.bb, c_fb, 0ull, c_col);
+}
+
+// Blocks of the iteration pass: a fixed grid (two blocks per CU fit its
+// LDS) that works through the list in block-sized chunks.
+constexpr int NL_GRID = 512;
+
+// k_alpha_newton (iteration pass): per list entry the node's populations
+// again (pulled as in k_alpha, kept in a thread-private LDS column), x_p,
+// (LEARN) the learned starter for entries whose series root was rejected,
+// Newton (or Halley) from the starter to the stopping rule, the viscosity
+// and alpha * beta.  Whole blocks walk the list together, so the matrix-core
+// section runs on whole waves (lanes past the end carry no features).
 template <typename T, typename F, int C, bool LEARN>
-__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F> a, Model M, MlpDev W, int record) {
-  // thread-private LDS: populations of the current component (column p * BLK
-  // + tid) and, per wave, x_p (column p * 64 + lane), whose 9.5 KB also hold
-  // the starter's two [64][32] bf16 tiles before the alpha solve
+__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha_newton(Ptrs<T, F> a, Model M, MlpDev W,
+                                                                             int record) {
+  // thread-private LDS: populations (column p * BLK + tid) and, per wave,
+  // x_p (column p * 64 + lane), whose 9.5 KB also hold the starter's two
+  // [64][32] bf16 tiles before the alpha solve
   __shared__ T lds_f[NQ * BLK];
   __shared__ __align__(16) double lds_x[NQ * BLK];
   __shared__ __align__(16) LearnLds<LEARN> learn;
   if constexpr (LEARN) mlp_stage(W, learn.net);
-  Node nd;
-  if (a.tx) decode_tile(a, nd);
-  else decode(a, nd);
+  const int count = *a.nl_count;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned long long c_fb = 0, c_it = 0, c_col = 0;
-  const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
-  const bool fl = nd.live && k == K_FLUID;
-  int nl[NQ];
-  unsigned solid = 0u;
-  if (fl) {
-    // ---- neighbours: local index, solid-or-outside flag
-    nl[0] = nd.n;
-    solid = a.nbm[nd.g];
-#pragma unroll
-    for (int p = 1; p < NQ; ++p) {
-      nl[p] = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
-      if (nl[p] < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
-    }
-  }
   T *f = lds_f + threadIdx.x;
   double *xs = lds_x + wv * (NQ * 64) + lane;
-#pragma unroll
-  for (int s = 0; s < C; ++s) {
-    // ---- pulled populations and their moments.  The moments are summed in
-    // FP64 whatever the storage: the equilibrium of the alpha solve must carry
-    // exactly the density and momentum of f (sum Delta = 0), or the rounding
-    // of an FP32 sum swamps the O(|Delta|^2) entropy balance.
+  const bool halley = M.alpha_iter == ELBM_ITER_HALLEY;
+  for (int base = blockIdx.x * BLK; base < count; base += gridDim.x * BLK) {
+    const int i = base + threadIdx.x;
+    const bool act = i < count;
+    int64_t g = 0;
+    int s = 0, bb = -1;
+    BoxDev B;
+    int x = 0, y = 0, z = 0, n = 0;
     double dr = 1.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    if (fl) {
+    AlphaSetup st{};
+    if (act) {
+      const uint32_t code = a.nl_idx[i];
+      g = C == 2 ? (int64_t)(code >> 1) : (int64_t)code;
+      s = C == 2 ? (int)(code & 1u) : 0;
+      bb = a.block_box[g / BLK];  // 256-node blocks never straddle a box
+      B = a.boxes[bb];
+      n = (int)(g - B.off);
+      x = n % B.nx;
+      const int r = n / B.nx;
+      y = r % B.ny;
+      z = r / B.ny;
+      const uint32_t solid = a.nbm[g];
       dr = 0.0;
 #pragma unroll
       for (int p = 0; p < NQ; ++p) {
-        const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
+        const int q = opp(p);
         const bool bounce = (p != 0) && ((solid >> q) & 1u);
-        const T v = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g]
-                           : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + nl[q]];
+        const int m = p ? nbr(B, x, y, z, kCx[q], kCy[q], kCz[q]) : n;
+        const T v = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + g] : a.fa[(int64_t)(s * NQ + p) * a.N + B.off + m];
         f[p * BLK] = v;
         const double dv = double(v);
         dr += dv;
@@ -493,88 +647,72 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         jy += double(kCy[p]) * dv;
         jz += double(kCz[p]) * dv;
       }
+      st.L = a.nl_L[i];
+      st.amax = a.nl_amax[i];
+      st.M2 = a.nl_M2[i];
+      const double sa = a.nl_a[i];
+      st.a = fabs(sa);
+      st.want_learned = sa < 0.0;
+      st.state = 0;
     }
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
-    // ---- alpha set-up at the component's own velocity (FP64)
-    AlphaSetup st{};
-    if (fl) st = alpha_setup<T>(f, xs, dr, ux, uy, uz, M.alpha_guess, M.rtol);
+    if (act) refill_x<T>(f, xs, dr, ux, uy, uz);
     double a0 = 2.0;
     if constexpr (LEARN) {
-      // ---- learned starter on the matrix cores, for waves holding a node
-      // where the series starter was rejected.  Its bf16 tiles overlay the
-      // wave's x scratch, which is refilled afterwards.
-      const bool want = fl && st.want_learned;
+      // ---- learned starter on the matrix cores, for waves holding an entry
+      // whose series root was rejected.  Its bf16 tiles overlay the wave's x
+      // scratch, which is refilled afterwards.
+      const bool want = act && st.want_learned;
       if (__ballot(want) != 0) {
-        float z[MLP_IN];
+        float zf[MLP_IN];
         double sc = 0.0;
         bool valid = false;
-        if (want) valid = features_from_x(xs, z, sc);
-        z[NQ] = float(sc);
+        if (want) valid = features_from_x(xs, zf, sc);
+        zf[NQ] = float(sc);
         wave_sync();
         __bf16 *tile = reinterpret_cast<__bf16 *>(lds_x + wv * (NQ * 64));
-        put_features(tile, lane, z, valid);
-        const float y = mlp_forward_wave(learn.net, tile, tile + 64 * 32, lane);
-        if (valid) a0 = 2.0 + sc * double(y);
-        if (fl) refill_x<T>(f, xs, dr, ux, uy, uz);
+        put_features(tile, lane, zf, valid);
+        const float yv = mlp_forward_wave(learn.net, tile, tile + 64 * 32, lane);
+        if (valid) a0 = 2.0 + sc * double(yv);
+        wave_sync();
+        if (act) refill_x<T>(f, xs, dr, ux, uy, uz);
       }
     }
-    if (fl) {
-      // ---- alpha: Newton polish from the starter
-      const double uu = ux * ux + uy * uy + uz * uz;
+    unsigned long long c_fb = 0, c_it = 0, c_col = 0;
+    if (act) {
       int its;
-      const double al = alpha_newton<T>(f, xs, st, a0, M.rtol, M.newton_max, its, M.alpha_iter == ELBM_ITER_HALLEY);
-      c_col += 1;
-      if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
-      // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root,
-      // evaluated in the field precision
-      using R = F;
-      double nu = M.nu0;
+      const double al = alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), M.rtol, M.newton_max,
+                                         its, halley);
+      c_col = 1;
+      if (its < 0) c_fb = 1;
+      else c_it = (unsigned long long)its;
+      double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (M.carreau) {
-        // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
-        // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
-        double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
 #pragma unroll 1
         for (int p = 0; p < NQ; ++p) {
           const double d = double(f[p * BLK]);
-          P00 += d * double(kCx[p] * kCx[p]);
-          P11 += d * double(kCy[p] * kCy[p]);
-          P22 += d * double(kCz[p] * kCz[p]);
-          P01 += d * double(kCx[p] * kCy[p]);
-          P02 += d * double(kCx[p] * kCz[p]);
-          P12 += d * double(kCy[p] * kCz[p]);
+          P[0] += d * double(kCx[p] * kCx[p]);
+          P[1] += d * double(kCy[p] * kCy[p]);
+          P[2] += d * double(kCz[p] * kCz[p]);
+          P[3] += d * double(kCx[p] * kCy[p]);
+          P[4] += d * double(kCx[p] * kCz[p]);
+          P[5] += d * double(kCy[p] * kCz[p]);
         }
-        P00 -= dr * (CS2 + ux * ux);
-        P11 -= dr * (CS2 + uy * uy);
-        P22 -= dr * (CS2 + uz * uz);
-        P01 -= dr * (ux * uy);
-        P02 -= dr * (ux * uz);
-        P12 -= dr * (uy * uz);
-        const R Pn = sym3_norm2<R>(R(P00), R(P11), R(P22), R(P01), R(P02), R(P12));
-        const R nf = R(nd.B.n_flow);
-        const R gd = shear_rate<R>(Pn, R(dr), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
-        const R lg = R(M.lam) * gd;
-        nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow1p<R>(lg * lg, R(0.5) * (nf - R(1))));
+        P[0] -= dr * (CS2 + ux * ux);
+        P[1] -= dr * (CS2 + uy * uy);
+        P[2] -= dr * (CS2 + uz * uz);
+        P[3] -= dr * (ux * uy);
+        P[4] -= dr * (ux * uz);
+        P[5] -= dr * (uy * uz);
       }
-      a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
+      const double nu = viscosity<F>(M, B.n_flow, P[0], P[1], P[2], P[3], P[4], P[5], dr, al);
+      a.ab[(int64_t)s * a.N + g] = al * (CS2 / (2.0 * nu + CS2));
       if (record) {
-        a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
-        a.rec_iters[(int64_t)s * a.N + nd.g] = its;
+        a.rec_alpha[(int64_t)s * a.N + g] = al;
+        a.rec_iters[(int64_t)s * a.N + g] = its;
       }
-    } else if (nd.live && record) {
-      a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
-      a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
     }
-  }
-  // ---- counters: wave sums, one atomic per wave and counter
-  c_fb = wave_sum_u64(c_fb);
-  c_it = wave_sum_u64(c_it);
-  c_col = wave_sum_u64(c_col);
-  if (lane == 0) {
-    unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
-    if (c_fb) atomicAdd(cn + 0, c_fb);
-    if (c_it) atomicAdd(cn + 1, c_it);
-    if (c_col) atomicAdd(cn + 4, c_col);
-    if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(a.err, ERR_ALPHA);
+    alpha_counters(a.cnt, a.err, M, act, bb, c_fb, c_it, c_col);
   }
 }
 

@@ -94,6 +94,10 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # the HIP runtime comes up through torch first: the library's calls then
+    # share the process's device view (loading the library first left its
+    # runtime without a device on the MI355X machine)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"libelbm.so not built at {path}; run __graft_entry__.build()")
     L = ct.CDLL(path)
