@@ -42,10 +42,11 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 4u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
+#define ELBM_ABI_VERSION 5u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
                                  3: sweep_priority in elbm_launch;
                                  4: Poisson stop rule and residual, strict error flags, Halley
-                                    iteration, electric force and solver fields in elbm_diag */
+                                    iteration, electric force and solver fields in elbm_diag;
+                                 5: the lattice (D3Q19 or the paper's D2Q9) in elbm_params */
 
 typedef struct elbm_ctx elbm_ctx;
 
@@ -67,6 +68,13 @@ typedef enum {
  * populations (always), set the sticky error word that elbm_sync reports.
  * Without them the conditions are only counted (elbm_diag). */
 enum { ELBM_STRICT_NEGPOP = 1, ELBM_STRICT_ALPHA = 2 };
+
+/* Lattice (Sec. II, Eq. lattice-b): D3Q19, or D2Q9, the paper's own 2-D
+ * lattice (p = 0 rest; 1..4 = +x, -x, +y, -y; 5..8 = (+1,+1), (-1,-1),
+ * (+1,-1), (-1,+1); weights 4/9, 1/9, 1/36).  A D2Q9 box is one x-y plane:
+ * nz = 1 and bounded in z (the Poisson problem then has no z faces);
+ * populations are [C][9][N]. */
+enum { ELBM_LATTICE_D3Q19 = 0, ELBM_LATTICE_D2Q9 = 1 };
 
 /* Storage: F64 = FP64 populations and fields; F32 = FP32 populations with
  * FP64 auxiliary fields (densities, psi, charge, potential, |E|^2);
@@ -118,11 +126,14 @@ typedef struct {
     int32_t sor_check_every;  /* with sor_tol > 0: residual checked after every so
                                  many sweeps (0: after the last only)              */
     int32_t alpha_iter;       /* ELBM_ITER_*                                        */
+    int32_t lattice;          /* ELBM_LATTICE_* (the learned starter: D3Q19 only)    */
+    int32_t pad2_;
 } elbm_params;
 
 /* One lattice box.  Boxes of one context are independent (no exchange). */
 typedef struct {
-    int32_t nx, ny, nz;       /* >= 2 each; a periodic axis must have even length   */
+    int32_t nx, ny, nz;       /* >= 2 each (D2Q9: nz = 1); a periodic axis must have
+                                 even length                                        */
     int32_t periodic[3];      /* 1 = periodic along x, y, z; 0 = bounded            */
     double E_ext[3];          /* uniform external field                             */
     double Q_b, Q_s;          /* bulk and surface charge (conserving model)         */

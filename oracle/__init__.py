@@ -46,7 +46,7 @@ class OraParams(ct.Structure):
         ("E_ext", ct.c_double * 3),
         ("sor_omega", ct.c_double), ("newton_rtol", ct.c_double),
         ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
-        ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("pad2_", ct.c_int32),
+        ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("lattice", ct.c_int32),
     ]
 
 
@@ -82,6 +82,12 @@ def lib():
         L.ora_shear_rate.restype = ct.c_double
         L.ora_shear_rate.argtypes = [ct.c_double] * 7
         L.ora_lattice.argtypes = [ct.c_void_p, ct.c_void_p]
+        L.ora_lattice_q.restype = ct.c_int
+        L.ora_lattice_q.argtypes = [ct.c_int, ct.c_void_p, ct.c_void_p]
+        L.ora_feq_lat.argtypes = [ct.c_int, ct.c_double, dp, dp]
+        L.ora_alpha_lat.restype = ct.c_double
+        L.ora_alpha_lat.argtypes = [ct.c_int, dp, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int,
+                                    ct.POINTER(ct.c_int)]
         L.ora_threads.restype = ct.c_int
         L.ora_poisson.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                   ct.c_double]
@@ -103,26 +109,31 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(ct.POINTER(ct.c_double))
 
 
-def lattice():
-    c = np.zeros((Q, 3), dtype=np.int32)
-    w = np.zeros(Q)
-    lib().ora_lattice(c.ctypes.data, w.ctypes.data)
+def nq(lattice: int = 0) -> int:
+    """Number of lattice directions: 19 (D3Q19, lattice 0) or 9 (D2Q9, lattice 1)."""
+    return 9 if lattice == 1 else 19
+
+
+def lattice(lat: int = 0):
+    q = nq(lat)
+    c = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q)
+    assert lib().ora_lattice_q(int(lat), c.ctypes.data, w.ctypes.data) == q
     return c, w
 
 
-def feq(rho: float, u) -> np.ndarray:
+def feq(rho: float, u, lat: int = 0) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.float64)
-    out = np.zeros(Q)
-    lib().ora_feq(rho, _dptr(u), _dptr(out))
+    out = np.zeros(nq(lat))
+    lib().ora_feq_lat(int(lat), rho, _dptr(u), _dptr(out))
     return out
 
 
-def alpha(f, fe, u, rho, alpha0=2.0, rtol=1e-12, maxit=30):
+def alpha(f, fe, u, rho, alpha0=2.0, rtol=1e-12, maxit=30, lat: int = 0):
     f = np.ascontiguousarray(f, dtype=np.float64)
     fe = np.ascontiguousarray(fe, dtype=np.float64)
-    u = np.ascontiguousarray(u, dtype=np.float64)
     it = ct.c_int(0)
-    a = lib().ora_alpha(_dptr(f), _dptr(fe), _dptr(u), rho, alpha0, rtol, maxit, ct.byref(it))
+    a = lib().ora_alpha_lat(int(lat), _dptr(f), _dptr(fe), rho, alpha0, rtol, maxit, ct.byref(it))
     return a, it.value
 
 
@@ -166,6 +177,7 @@ def make_params(p, box, nthreads: int = 0) -> OraParams:
     P.newton_rtol = p.newton_rtol
     P.sor_tol = float(getattr(p, "sor_tol", 0.0))
     P.sor_check_every = int(getattr(p, "sor_check_every", 0))
+    P.lattice = int(getattr(p, "lattice", 0))
     for s in range(2):
         P.rho_in[s] = p.rho_in[s]
         P.rho_out[s] = p.rho_out[s]
@@ -178,6 +190,7 @@ class Oracle:
     def __init__(self, params, box, nthreads: int = 0):
         self.p, self.box = params, box
         self.C = params.ncomp
+        self.Q = nq(int(getattr(params, "lattice", 0)))
         self.N = box.n
         self.shape = (box.nz, box.ny, box.nx)
         self._P = make_params(params, box, nthreads)
@@ -189,7 +202,7 @@ class Oracle:
                               self._ubc.ctypes.data)
         rho0 = np.ascontiguousarray(box.rho0.reshape(self.C, -1), dtype=np.float64)
         u0 = np.ascontiguousarray(box.u0.reshape(3, -1), dtype=np.float64)
-        xi = np.ascontiguousarray(box.xi.reshape(self.C, Q, -1), dtype=np.float64)
+        xi = np.ascontiguousarray(box.xi.reshape(self.C, self.Q, -1), dtype=np.float64)
         L.ora_init(self.h, rho0.ctypes.data, u0.ctypes.data, xi.ctypes.data, float(box.jitter))
 
     def __del__(self):
@@ -207,7 +220,7 @@ class Oracle:
 
     def field(self, which: int) -> np.ndarray:
         kind = self._COUNTS[which]
-        lead = {"C": (self.C,), "C3": (self.C, 3), "3": (3,), "1": (), "CQ": (self.C, Q)}[kind]
+        lead = {"C": (self.C,), "C3": (self.C, 3), "3": (3,), "1": (), "CQ": (self.C, self.Q)}[kind]
         out = np.zeros(lead + self.shape)
         lib().ora_field(self.h, which, out.ctypes.data)
         return out

@@ -36,23 +36,50 @@
 #include <omp.h>
 #endif
 
-#define Q 19
+#define QMAX 19
 #define CS2 (1.0 / 3.0)
 
-/* D3Q19 velocities: rest, the 6 face neighbours, the 12 edge neighbours;
- * opposite directions sit at adjacent (odd, even) indices.  The paper's
- * D2Q9 weights 4/9, 1/9, 1/36 become 1/3, 1/18, 1/36 in 3-D (same c_s^2 = 1/3). */
-static const int CV[Q][3] = {
-    {0, 0, 0},
-    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
-    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
-    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-static const double WV[Q] = {
-    1.0 / 3.0,
-    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
-    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
-    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* Lattices (Sec. II, Eq. lattice-b and the weights below it).  D3Q19:
+ * rest, the 6 face neighbours, the 12 edge neighbours; the paper's D2Q9
+ * weights 4/9, 1/9, 1/36 become 1/3, 1/18, 1/36 in 3-D (same c_s^2 = 1/3).
+ * D2Q9 (the paper's own lattice): rest, 4 axis and 4 diagonal neighbours in
+ * the x-y plane (c_z = 0; a 2-D box has nz = 1, bounded in z).  Opposite
+ * directions sit at adjacent (odd, even) indices in both. */
+typedef struct {
+    int q;
+    int c[QMAX][3];
+    double w[QMAX];
+} ora_lat;
+
+static const ora_lat LAT_D3Q19 = {
+    19,
+    {{0, 0, 0},
+     {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+     {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+     {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}},
+    {1.0 / 3.0,
+     1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0}};
+
+static const ora_lat LAT_D2Q9 = {
+    9,
+    {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}},
+    {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0}};
+
+static const ora_lat *lattice_of(int id) { return id == 1 ? &LAT_D2Q9 : &LAT_D3Q19; }
+
+/* The state's lattice under the names the stage functions use. */
+#define LAT_LOCALS(st)                                                                   \
+    const int Q = (st)->Q;                                                               \
+    const int(*CV)[3] = (st)->lat->c;                                                    \
+    const double *WV = (st)->lat->w;                                                     \
+    (void)Q;                                                                             \
+    (void)CV;                                                                            \
+    (void)WV
 
 static int opposite(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
 
@@ -74,11 +101,14 @@ typedef struct {
      * most sor_tol * max|rhs| (checked after every sor_check_every sweeps when
      * that is > 0, and after the last one); sor_tol = 0: exactly sor_sweeps */
     double sor_tol;
-    int32_t sor_check_every, pad2_;
+    int32_t sor_check_every;
+    int32_t lattice;  /* 0: D3Q19, 1: D2Q9 (nz = 1, bounded in z) */
 } ora_params;
 
 typedef struct {
     ora_params P;
+    const ora_lat *lat;
+    int Q;
     int64_t N;
     int C;
     uint8_t *type;
@@ -153,12 +183,16 @@ static int is_solid(const ora_state *s, int64_t n) { return n < 0 || kind(s, n) 
 /* ---------------------------------------------------- node-level maths */
 
 /* Second-order equilibrium (Sec. II, the Mach expansion below Eq. lattice-b). */
-void ora_feq(double rho, const double u[3], double out[Q]) {
+static void feq_lat(const ora_lat *L, double rho, const double u[3], double *out) {
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    for (int p = 0; p < Q; ++p) {
-        double cu = CV[p][0] * u[0] + CV[p][1] * u[1] + CV[p][2] * u[2];
-        out[p] = WV[p] * rho * (1.0 + cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2));
+    for (int p = 0; p < L->q; ++p) {
+        double cu = L->c[p][0] * u[0] + L->c[p][1] * u[1] + L->c[p][2] * u[2];
+        out[p] = L->w[p] * rho * (1.0 + cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2));
     }
+}
+void ora_feq(double rho, const double u[3], double out[19]) { feq_lat(&LAT_D3Q19, rho, u, out); }
+void ora_feq_lat(int lattice, double rho, const double u[3], double *out) {
+    feq_lat(lattice_of(lattice), rho, u, out);
 }
 
 /* phi(y) = (1+y) ln(1+y) - y, accurate for small |y| (its Taylor series
@@ -200,7 +234,7 @@ static double phi_fn(double y) {
  * Returns the number of Newton updates (>= 0) or -1 on fallback.
  */
 /* g at the top of the positivity interval (see ora_alpha): phi(-1) = 1. */
-static double g_at_alpha_max(const double f[Q], const double x[Q], double L, double amax) {
+static double g_at_alpha_max(int Q, const double *f, const double *x, double L, double amax) {
     double S = 0.0;
     for (int p = 0; p < Q; ++p) {
         double y = amax * x[p];
@@ -209,9 +243,11 @@ static double g_at_alpha_max(const double f[Q], const double x[Q], double L, dou
     return S + amax * L;
 }
 
-double ora_alpha(const double f[Q], const double feq[Q], const double u[3], double rho,
-                 double alpha0, double rtol, int maxit, int *iters_out) {
-    double D[Q], x[Q];
+static double alpha_lat(const ora_lat *lat, const double *f, const double *feq, double rho,
+                        double alpha0, double rtol, int maxit, int *iters_out) {
+    const int Q = lat->q;
+    const double *WV = lat->w;
+    double D[QMAX], x[QMAX];
     double xmax = 0.0, amax = INFINITY;
     int nonpos = 0;
     for (int p = 0; p < Q; ++p) {
@@ -230,7 +266,6 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
      * where the polynomial equilibrium is negative */
     double L = 0.0;
     for (int p = 0; p < Q; ++p) L += D[p] * log1p((f[p] - WV[p] * rho) / (WV[p] * rho));
-    (void)u;
     double a = alpha0;
     if (!(a > 0.0 && a < amax)) a = 0.5 * (amax < 4.0 ? amax : 4.0);
     if (L < 0.0) {
@@ -250,7 +285,7 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
             if (an >= amax) {
                 if (!probed) {  /* leaving at the top: is there a root at all? */
                     probed = 1;
-                    if (!(g_at_alpha_max(f, x, L, amax) > 0.0)) break;
+                    if (!(g_at_alpha_max(Q, f, x, L, amax) > 0.0)) break;
                 }
                 an = 0.5 * (a + amax);
             }
@@ -261,6 +296,16 @@ double ora_alpha(const double f[Q], const double feq[Q], const double u[3], doub
     }
     *iters_out = -1;
     return fmin(2.0, 0.99 * amax);
+}
+
+double ora_alpha(const double f[19], const double feq[19], const double u[3], double rho,
+                 double alpha0, double rtol, int maxit, int *iters_out) {
+    (void)u;
+    return alpha_lat(&LAT_D3Q19, f, feq, rho, alpha0, rtol, maxit, iters_out);
+}
+double ora_alpha_lat(int lattice, const double *f, const double *feq, double rho, double alpha0,
+                     double rtol, int maxit, int *iters_out) {
+    return alpha_lat(lattice_of(lattice), f, feq, rho, alpha0, rtol, maxit, iters_out);
 }
 
 /* Largest |eigenvalue| of a symmetric 3x3 matrix (the matrix 2-norm) by
@@ -336,6 +381,9 @@ static void *xcalloc(size_t n, size_t sz) { return calloc(n ? n : 1, sz); }
 ora_state *ora_create(const ora_params *P, const uint8_t *type, const double *phi0,
                       const double *u_bc) {
     ora_state *s = (ora_state *)calloc(1, sizeof(ora_state));
+    s->lat = lattice_of(P->lattice);
+    s->Q = s->lat->q;
+    LAT_LOCALS(s);
     s->P = *P;
     s->C = P->ncomp;
     s->N = (int64_t)P->nx * P->ny * P->nz;
@@ -391,7 +439,8 @@ void ora_destroy(ora_state *s) {
 /* Initial boundary-node populations: inlet nodes f_eq(rho_in, u_bc), outlet
  * nodes f_eq(rho_out, 0).  Neither streams nor collides; outlet nodes keep
  * theirs, inlet nodes are reset every step (see inlet_populations). */
-static void boundary_populations(ora_state *s, int64_t n, int sigma, double out[Q]) {
+static void boundary_populations(ora_state *s, int64_t n, int sigma, double *out) {
+    LAT_LOCALS(s);
     double u[3] = {0, 0, 0};
     double r;
     if (kind(s, n) == T_INLET) {
@@ -400,16 +449,17 @@ static void boundary_populations(ora_state *s, int64_t n, int sigma, double out[
     } else {
         r = s->P.rho_out[sigma];
     }
-    ora_feq(r, u, out);
+    feq_lat(s->lat, r, u, out);
 }
 
 /* Initial state: f = f_eq(rho, u) (1 + amp * xi) at fluid nodes;
  * boundary nodes get their fixed equilibria; solid nodes hold zeros. */
 void ora_init(ora_state *s, const double *rho0, const double *u0, const double *xi, double amp) {
+    LAT_LOCALS(s);
     int64_t N = s->N;
     for (int sg = 0; sg < s->C; ++sg)
         for (int64_t n = 0; n < N; ++n) {
-            double fe[Q];
+            double fe[QMAX];
             int k = kind(s, n);
             if (k == T_SOLID) {
                 for (int p = 0; p < Q; ++p) s->f[((int64_t)sg * Q + p) * N + n] = 0.0;
@@ -421,7 +471,7 @@ void ora_init(ora_state *s, const double *rho0, const double *u0, const double *
                 continue;
             }
             double u[3] = {u0[n], u0[N + n], u0[2 * N + n]};
-            ora_feq(rho0[(int64_t)sg * N + n], u, fe);
+            feq_lat(s->lat, rho0[(int64_t)sg * N + n], u, fe);
             for (int p = 0; p < Q; ++p) {
                 double j = xi ? xi[((int64_t)sg * Q + p) * N + n] : 0.0;
                 s->f[((int64_t)sg * Q + p) * N + n] = fe[p] * (1.0 + amp * j);
@@ -435,6 +485,7 @@ void ora_init(ora_state *s, const double *rho0, const double *u0, const double *
 /* Streaming (left-hand side of Eq. lattice-b) by pulling, halfway
  * bounce-back at solid nodes; moments rho = sum f, j = sum c f. */
 static void stream_and_moments(ora_state *s) {
+    LAT_LOCALS(s);
     const int64_t N = s->N;
     const int C = s->C;
 #pragma omp parallel for schedule(static)
@@ -479,6 +530,7 @@ static void stream_and_moments(ora_state *s) {
  * mode 1: only an outside neighbour takes the centre value. */
 static void gradient19(const ora_state *s, const double *X, int x, int y, int z, int mode,
                        double out[3]) {
+    LAT_LOCALS(s);
     int64_t n = node_index(s, x, y, z);
     double g0 = 0, g1 = 0, g2 = 0;
     for (int p = 1; p < Q; ++p) {
@@ -498,6 +550,7 @@ static void gradient19(const ora_state *s, const double *X, int x, int y, int z,
  * with the sign that makes a convex drop positive: K = -div n), the smoothed
  * Heaviside theta and the two charge weights. */
 static void interface_fields(ora_state *s) {
+    LAT_LOCALS(s);
     const int64_t N = s->N;
     const double *rA = s->rho;
 #pragma omp parallel for schedule(static)
@@ -741,6 +794,7 @@ static void electric(ora_state *s) {
  * psi = 1 - exp(-rho) (rho_0 = 1).  The electric force is shared among the
  * components by mass fraction.  Total F^s = F_int^s + F_el^s. */
 static void forces(ora_state *s) {
+    LAT_LOCALS(s);
     const int64_t N = s->N;
     const int C = s->C;
 #pragma omp parallel for schedule(static)
@@ -784,7 +838,8 @@ static void forces(ora_state *s) {
  * inlet node holds f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted
  * mean density of its fluid neighbours, sum_p w_p rho(r + c_p) / sum_p w_p
  * (rho_in when it has none). */
-static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, double out[Q]) {
+static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, double *out) {
+    LAT_LOCALS(s);
     const int64_t N = s->N;
     const int64_t n = node_index(s, x, y, z);
     double sw = 0.0, sr = 0.0;
@@ -795,7 +850,7 @@ static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, d
         sr += WV[p] * s->rho[(int64_t)sg * N + m];
     }
     double u[3] = {s->u_bc[n], s->u_bc[N + n], s->u_bc[2 * N + n]};
-    ora_feq(sw > 0.0 ? sr / sw : s->P.rho_in[sg], u, out);
+    feq_lat(s->lat, sw > 0.0 ? sr / sw : s->P.rho_in[sg], u, out);
 }
 
 /* Collision (Eq. lattice-b) with alpha (Eq. entropic), beta from the
@@ -804,6 +859,7 @@ static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, d
  * (Eq. add).  Each component relaxes to the equilibrium at its own
  * velocity j/rho. */
 static void collide(ora_state *s) {
+    LAT_LOCALS(s);
     const int64_t N = s->N;
     const int C = s->C;
     int64_t nfb = 0, nnf = 0, nneg = 0;
@@ -828,7 +884,7 @@ static void collide(ora_state *s) {
                         /* outlet and solid nodes keep their populations; inlet nodes are reset */
                         const double *fs = s->f + (int64_t)sg * Q * N;
                         if (k == T_INLET) {
-                            double fi[Q];
+                            double fi[QMAX];
                             inlet_populations(s, x, y, z, sg, fi);
                             for (int p = 0; p < Q; ++p) fo[p * N + n] = fi[p];
                         } else {
@@ -839,14 +895,14 @@ static void collide(ora_state *s) {
                         s->nu[(int64_t)sg * N + n] = 0.0;
                         continue;
                     }
-                    double f[Q], fe[Q], u[3];
+                    double f[QMAX], fe[QMAX], u[3];
                     const double *fp = s->fp + (int64_t)sg * Q * N;
                     for (int p = 0; p < Q; ++p) f[p] = fp[p * N + n];
                     double r = s->rho[(int64_t)sg * N + n];
                     for (int a = 0; a < 3; ++a) u[a] = s->jm[((int64_t)sg * 3 + a) * N + n] / r;
-                    ora_feq(r, u, fe);
+                    feq_lat(s->lat, r, u, fe);
                     int its;
-                    double al = ora_alpha(f, fe, u, r, 2.0, s->P.newton_rtol, s->P.newton_max, &its);
+                    double al = alpha_lat(s->lat, f, fe, r, 2.0, s->P.newton_rtol, s->P.newton_max, &its);
                     if (its < 0) nfb++;
                     s->alpha[(int64_t)sg * N + n] = al;
                     s->iters[(int64_t)sg * N + n] = its;
@@ -869,9 +925,9 @@ static void collide(ora_state *s) {
                     }
                     s->nu[(int64_t)sg * N + n] = nu;
                     double beta = CS2 / (2.0 * nu + CS2);
-                    double u2[3], fe2[Q];
+                    double u2[3], fe2[QMAX];
                     for (int a = 0; a < 3; ++a) u2[a] = u[a] + s->F[((int64_t)sg * 3 + a) * N + n] / r;
-                    ora_feq(r, u2, fe2);
+                    feq_lat(s->lat, r, u2, fe2);
                     for (int p = 0; p < Q; ++p) {
                         double v = f[p] + al * beta * (fe[p] - f[p]) + (fe2[p] - fe[p]);
                         if (!isfinite(v)) nnf++;
@@ -906,6 +962,7 @@ enum {
 
 /* Copies a stored field into out; returns the number of doubles written. */
 int64_t ora_field(const ora_state *s, int which, double *out) {
+    LAT_LOCALS(s);
     int64_t N = s->N, C = s->C;
     const double *src = NULL;
     int64_t cnt = 0;
@@ -939,6 +996,7 @@ int64_t ora_field(const ora_state *s, int which, double *out) {
 void ora_iters(const ora_state *s, int32_t *out) { memcpy(out, s->iters, s->C * s->N * sizeof(int32_t)); }
 
 void ora_set_populations(ora_state *s, const double *f) {
+    LAT_LOCALS(s);
     memcpy(s->f, f, (size_t)s->C * Q * s->N * sizeof(double));
 }
 void ora_set_phi(ora_state *s, const double *phi) { memcpy(s->phi, phi, s->N * sizeof(double)); }
@@ -957,12 +1015,21 @@ void ora_poisson_stats(const ora_state *s, double out_d[2], int64_t out_i[2]) {
     out_i[0] = s->sor_done; out_i[1] = s->sor_noconv;
 }
 
-/* Lattice tables (for the tests). */
-void ora_lattice(int32_t c[Q * 3], double w[Q]) {
-    for (int p = 0; p < Q; ++p) {
-        for (int a = 0; a < 3; ++a) c[p * 3 + a] = CV[p][a];
-        w[p] = WV[p];
+/* Lattice tables (for the tests): D3Q19. */
+void ora_lattice(int32_t c[19 * 3], double w[19]) {
+    for (int p = 0; p < 19; ++p) {
+        for (int a = 0; a < 3; ++a) c[p * 3 + a] = LAT_D3Q19.c[p][a];
+        w[p] = LAT_D3Q19.w[p];
     }
+}
+/* Tables of lattice `lattice` (0 D3Q19, 1 D2Q9); returns its Q. */
+int ora_lattice_q(int lattice, int32_t *c, double *w) {
+    const ora_lat *L = lattice_of(lattice);
+    for (int p = 0; p < L->q; ++p) {
+        for (int a = 0; a < 3; ++a) c[p * 3 + a] = L->c[p][a];
+        w[p] = L->w[p];
+    }
+    return L->q;
 }
 
 int ora_threads(void) {

@@ -39,12 +39,12 @@ struct elbm_ctx {
   std::vector<int32_t> block_box;
   int64_t Ntot = 0;
   int64_t maxN = 0;
+  int Q = 19;  // directions of the context's lattice
   int nblocks = 0;
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
   size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_nbm, o_reca,
-      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, o_nlc, o_nli, o_nlL,
-      o_nlA, o_nlM, o_nla, total;
+      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
@@ -168,12 +168,6 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.block_box = (const int32_t *)(b + c->o_bb);
   a.partials = (double *)(b + c->o_part);
   a.res_part = (double *)(b + c->o_rpart);
-  a.nl_count = (int32_t *)(b + c->o_nlc);
-  a.nl_idx = (uint32_t *)(b + c->o_nli);
-  a.nl_L = (double *)(b + c->o_nlL);
-  a.nl_amax = (double *)(b + c->o_nlA);
-  a.nl_M2 = (double *)(b + c->o_nlM);
-  a.nl_a = (double *)(b + c->o_nla);
   a.fel_part = (double *)(b + c->o_fpart);
   a.scal = (double *)(b + c->o_scal);
   a.cnt = (unsigned long long *)(b + c->o_cnt);
@@ -228,7 +222,7 @@ elbm_status collect_timing(elbm_ctx *c) {
 
 // Enqueues one time step (every kernel of Sec. II.C) on the bound stream and
 // flips the population parity.
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 elbm_status enqueue_step(elbm_ctx *c, int rec) {
   const Model M = make_model(c->P);
   const dim3 grid(c->nblocks), blk(BLK);
@@ -259,24 +253,27 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   const bool fork = !c->timing;
   hipStream_t as = fork ? c->aux : c->stream;
   mark(c, ev, 0);
-  hipLaunchKernelGGL((k_density<T, F, C>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_density<Lat, T, F, C>), grid, blk, 0, c->stream, a);
   mark(c, ev, 1);
-  // the two alpha passes: screening over every node, then the iteration list
-  auto alpha_passes = [&]() {
-    hipLaunchKernelGGL((k_alpha<T, F, C>), dim3(cgrid.x, C), blk, 0, as, a, M, rec);
-    if (M.alpha_guess == ELBM_GUESS_MLP)
-      hipLaunchKernelGGL((k_alpha_newton<T, F, C, true>), dim3(NL_GRID), blk, 0, as, a, M, make_mlp(c), rec);
-    else
-      hipLaunchKernelGGL((k_alpha_newton<T, F, C, false>), dim3(NL_GRID), blk, 0, as, a, M, make_mlp(c), rec);
+  // the alpha kernel (the learned starter reads the 19 D3Q19 ratios)
+  auto alpha_pass = [&]() {
+    bool learned = false;
+    if constexpr (Lat::Q == 19) {
+      if (M.alpha_guess == ELBM_GUESS_MLP) {
+        hipLaunchKernelGGL((k_alpha<Lat, T, F, C, true>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
+        learned = true;
+      }
+    }
+    if (!learned) hipLaunchKernelGGL((k_alpha<Lat, T, F, C, false>), cgrid, blk, 0, as, a, M, make_mlp(c), rec);
   };
   if (fork) {
     HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-    alpha_passes();
+    alpha_pass();
     HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   }
-  hipLaunchKernelGGL((k_gradient<T, F>), grid, blk, 0, c->stream, a);
-  hipLaunchKernelGGL((k_interface<T, F>), grid, blk, 0, c->stream, a, M);
+  hipLaunchKernelGGL((k_gradient<Lat, T, F>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_interface<Lat, T, F>), grid, blk, 0, c->stream, a, M);
   hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M, a.prio);
   hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 2);
@@ -305,15 +302,15 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     hipLaunchKernelGGL((k_phi_sub<T, F>), grid, blk, 0, c->stream, a);
   }
   mark(c, ev, 3);
-  hipLaunchKernelGGL((k_efield<T, F>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_efield<Lat, T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 4);
   if (fork) {
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   } else {
-    alpha_passes();
+    alpha_pass();
   }
   mark(c, ev, 5);
-  hipLaunchKernelGGL((k_collide<T, F, C>), grid, blk, 0, c->stream, a, M, rec);
+  hipLaunchKernelGGL((k_collide<Lat, T, F, C>), grid, blk, 0, c->stream, a, M, rec);
   mark(c, ev, 6);
   c->parity ^= 1;
   HIPCHK(c, hipGetLastError());
@@ -324,7 +321,7 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
 // unrecorded steps replay a captured two-step hipGraph (one per starting
 // parity, built on first use and kept with the context): the 2 x (7 + 2k)
 // launches of a pair become one graph launch.
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
   int direct = nsteps;
   if (!c->timing && c->use_graphs && c->stream != nullptr) {
@@ -336,7 +333,7 @@ elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
         elbm_status s2 = ELBM_OK;
-        for (int i = 0; i < k && !s2; ++i) s2 = enqueue_step<T, F, C>(c, 0);
+        for (int i = 0; i < k && !s2; ++i) s2 = enqueue_step<Lat, T, F, C>(c, 0);
         hipError_t ec = hipStreamEndCapture(c->stream, &g);
         if (s2) {
           if (g) (void)hipGraphDestroy(g);
@@ -355,13 +352,13 @@ elbm_status launch_steps(elbm_ctx *c, int nsteps, int record) {
     }
   }
   for (int it = 0; it < direct; ++it) {
-    elbm_status st = enqueue_step<T, F, C>(c, record && it == direct - 1);
+    elbm_status st = enqueue_step<Lat, T, F, C>(c, record && it == direct - 1);
     if (st) return st;
   }
   return ELBM_OK;
 }
 
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 elbm_status set_box_impl(elbm_ctx *c, int box, const uint8_t *type, const double *rho,
                          const double *u, const double *phi, const double *u_bc, const double *xi,
                          double jitter) {
@@ -381,19 +378,19 @@ elbm_status set_box_impl(elbm_ctx *c, int box, const uint8_t *type, const double
   const Model M = make_model(c->P);
   const dim3 grid((unsigned)((B.n + BLK - 1) / BLK)), blk(BLK);
   for (int s = 0; s < C; ++s)
-    for (int p = 0; p < NQ; ++p) {
+    for (int p = 0; p < Lat::Q; ++p) {
       const double *xp = nullptr;
       if (xi) {
-        HIPCHK(c, hipMemcpy(stage(c, 8), xi + ((size_t)s * NQ + p) * nb, nb * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(stage(c, 8), xi + ((size_t)s * Lat::Q + p) * nb, nb * 8, hipMemcpyHostToDevice));
         xp = stage(c, 8);
       }
-      hipLaunchKernelGGL((k_init_dir<T, F>), grid, blk, 0, c->stream, a, M, box, s, p, stage(c, 0), stage(c, 2),
+      hipLaunchKernelGGL((k_init_dir<Lat, T, F>), grid, blk, 0, c->stream, a, M, box, s, p, stage(c, 0), stage(c, 2),
                          u_bc ? stage(c, 5) : nullptr, xp, jitter, c->maxN);
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
   // neighbour masks (static geometry), for every box: cheap, and boxes set later redo them
-  hipLaunchKernelGGL((k_neighbour_mask<T, F>), dim3(c->nblocks), blk, 0, c->stream, a,
+  hipLaunchKernelGGL((k_neighbour_mask<Lat, T, F>), dim3(c->nblocks), blk, 0, c->stream, a,
                      (uint32_t *)(c->base + c->o_nbm));
   HIPCHK(c, hipGetLastError());
   // inlet velocity, kept for the step's inlet update
@@ -460,9 +457,9 @@ elbm_status check_box_arg(elbm_ctx *c, int box) {
 
 size_t cur_pop_off(const elbm_ctx *c) { return c->parity ? c->o_fb : c->o_fa; }
 
-// Runs the statement list with T (population type) and F (field type) bound
-// to the context's storage mode.
-#define ELBM_DISPATCH(c, ...)                                   \
+// Runs the statement list with L (lattice), T (population type) and F
+// (field type) bound to the context's lattice and storage mode.
+#define ELBM_DISPATCH_STORAGE(c, ...)                           \
   switch ((c)->P.storage) {                                     \
     case ELBM_STORAGE_F64: {                                    \
       using T = double;                                         \
@@ -479,6 +476,14 @@ size_t cur_pop_off(const elbm_ctx *c) { return c->parity ? c->o_fb : c->o_fa; }
       using F = float;                                          \
       __VA_ARGS__;                                              \
     }                                                           \
+  }
+#define ELBM_DISPATCH(c, ...)                                   \
+  if ((c)->P.lattice == ELBM_LATTICE_D2Q9) {                    \
+    using Lat = D2Q9;                                             \
+    ELBM_DISPATCH_STORAGE(c, __VA_ARGS__)                       \
+  } else {                                                      \
+    using Lat = D3Q19;                                            \
+    ELBM_DISPATCH_STORAGE(c, __VA_ARGS__)                       \
   }
 
 }  // namespace
@@ -498,6 +503,9 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   if (!(P->sor_tol >= 0.0) || P->sor_check_every < 0) return ELBM_EINVAL;
   if (P->strict < 0 || P->strict > (ELBM_STRICT_NEGPOP | ELBM_STRICT_ALPHA)) return ELBM_EINVAL;
   if (P->alpha_iter != ELBM_ITER_NEWTON && P->alpha_iter != ELBM_ITER_HALLEY) return ELBM_EINVAL;
+  if (P->lattice != ELBM_LATTICE_D3Q19 && P->lattice != ELBM_LATTICE_D2Q9) return ELBM_EINVAL;
+  const bool two_d = P->lattice == ELBM_LATTICE_D2Q9;
+  if (two_d && P->alpha_guess == ELBM_GUESS_MLP) return ELBM_EINVAL;  // the network reads 19 ratios
   if (P->charge_model != ELBM_CHARGE_CONSERVING && P->charge_model != ELBM_CHARGE_GENERATOR) return ELBM_EINVAL;
   if (!(P->w_theta > 0.0) || !(P->K_d > 0.0) || !(P->nu0 > 0.0) || !(P->newton_rtol > 0.0)) return ELBM_EINVAL;
   if (P->carreau && !(P->nu_inf > 0.0 && P->lam >= 0.0)) return ELBM_EINVAL;
@@ -507,13 +515,14 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   elbm_ctx *c = new (std::nothrow) elbm_ctx();
   if (!c) return ELBM_ENOMEM;
   c->P = *P;
+  c->Q = two_d ? D2Q9::Q : D3Q19::Q;
   c->esz_pop = P->storage == ELBM_STORAGE_F64 ? 8 : 4;
   c->esz_fld = P->storage == ELBM_STORAGE_F32_ALL ? 4 : 8;
   int64_t off = 0;
   int blk0 = 0;
   for (int b = 0; b < nboxes; ++b) {
     const elbm_box &x = boxes[b];
-    if (x.nx < 2 || x.ny < 2 || x.nz < 2) { delete c; return ELBM_EINVAL; }
+    if (x.nx < 2 || x.ny < 2 || (two_d ? (x.nz != 1 || x.periodic[2]) : x.nz < 2)) { delete c; return ELBM_EINVAL; }
     const int64_t n = (int64_t)x.nx * x.ny * x.nz;
     if (n > (int64_t)1 << 30) { delete c; return ELBM_EINVAL; }
     const int nn[3] = {x.nx, x.ny, x.nz};
@@ -556,8 +565,8 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   const size_t e = c->esz_fld, ep = c->esz_pop;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-  c->o_fa = take((size_t)C * NQ * N * ep);
-  c->o_fb = take((size_t)C * NQ * N * ep);
+  c->o_fa = take((size_t)C * c->Q * N * ep);
+  c->o_fb = take((size_t)C * c->Q * N * ep);
   c->o_rho = take((size_t)C * N * e);
   c->o_psi = take((size_t)C * N * e);
   c->o_grad = take(4 * (size_t)N * e);
@@ -583,12 +592,6 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_scal = take(sizeof(double) * NSCAL * nboxes);
   c->o_cnt = take(sizeof(unsigned long long) * NCNT * nboxes);
   c->o_err = take(sizeof(uint32_t) * 4);
-  c->o_nlc = take(sizeof(int32_t) * 4);
-  c->o_nli = take(sizeof(uint32_t) * (size_t)C * N);
-  c->o_nlL = take(sizeof(double) * (size_t)C * N);
-  c->o_nlA = take(sizeof(double) * (size_t)C * N);
-  c->o_nlM = take(sizeof(double) * (size_t)C * N);
-  c->o_nla = take(sizeof(double) * (size_t)C * N);
   c->o_mp = take(sizeof(float) * MLP_NPARAM);
   c->o_mm = take(sizeof(float) * MLP_NPARAM);
   c->o_mv = take(sizeof(float) * MLP_NPARAM);
@@ -669,7 +672,7 @@ elbm_status elbm_set_box(elbm_ctx *c, int32_t box, const uint8_t *type, const do
   c->any_gauge = false;
   for (auto &d : c->bdev) if (!d.has_dirichlet) c->any_gauge = true;
   HIPCHK(c, hipMemcpy(c->base + c->o_boxes + sizeof(BoxDev) * box, &B, sizeof(BoxDev), hipMemcpyHostToDevice));
-  ELBM_DISPATCH(c, return set_box_impl<T, F>(c, box, type, rho, u, phi, u_bc, xi, jitter))
+  ELBM_DISPATCH(c, return set_box_impl<Lat, T, F>(c, box, type, rho, u, phi, u_bc, xi, jitter))
 }
 
 elbm_status elbm_step(elbm_ctx *c, int32_t nsteps, int32_t record) {
@@ -678,9 +681,9 @@ elbm_status elbm_step(elbm_ctx *c, int32_t nsteps, int32_t record) {
   if (nsteps < 0) return fail(c, ELBM_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return ELBM_OK;
   if (c->P.ncomp == 2) {
-    ELBM_DISPATCH(c, return launch_steps<T, F, 2>(c, nsteps, record))
+    ELBM_DISPATCH(c, return launch_steps<Lat, T, F, 2>(c, nsteps, record))
   }
-  ELBM_DISPATCH(c, return launch_steps<T, F, 1>(c, nsteps, record))
+  ELBM_DISPATCH(c, return launch_steps<Lat, T, F, 1>(c, nsteps, record))
 }
 
 elbm_status elbm_set_graphs(elbm_ctx *c, int32_t enable) {
@@ -852,7 +855,7 @@ elbm_status elbm_get_populations(elbm_ctx *c, int32_t box, double *f) {
   elbm_status st = check_box_arg(c, box);
   if (st) return st;
   if (!f) return fail(c, ELBM_EINVAL, "f is NULL");
-  const int np = c->P.ncomp * NQ;
+  const int np = c->P.ncomp * c->Q;
   ELBM_DISPATCH(c, return read_planes<T>(c, box, cur_pop_off(c), np, f))
 }
 
@@ -860,7 +863,7 @@ elbm_status elbm_set_populations(elbm_ctx *c, int32_t box, const double *f) {
   elbm_status st = check_box_arg(c, box);
   if (st) return st;
   if (!f) return fail(c, ELBM_EINVAL, "f is NULL");
-  const int np = c->P.ncomp * NQ;
+  const int np = c->P.ncomp * c->Q;
   const size_t other = c->parity ? c->o_fa : c->o_fb;
   ELBM_DISPATCH(c, return write_planes<T>(c, box, cur_pop_off(c), other, np, f))
 }
@@ -884,8 +887,8 @@ elbm_status elbm_diagnostics(elbm_ctx *c, int32_t box, elbm_diag *out) {
   double *dst = stage(c, 0);
   ELBM_DISPATCH(c, {
     Ptrs<T, F> a = make_ptrs<T, F>(c);
-    if (c->P.ncomp == 2) hipLaunchKernelGGL((k_diag<T, F, 2>), grid, blk, 0, c->stream, a, box, dst);
-    else hipLaunchKernelGGL((k_diag<T, F, 1>), grid, blk, 0, c->stream, a, box, dst);
+    if (c->P.ncomp == 2) hipLaunchKernelGGL((k_diag<Lat, T, F, 2>), grid, blk, 0, c->stream, a, box, dst);
+    else hipLaunchKernelGGL((k_diag<Lat, T, F, 1>), grid, blk, 0, c->stream, a, box, dst);
   } break)
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1043,6 +1046,7 @@ elbm_status elbm_alpha_samples(elbm_ctx *c, int32_t box, void *dFeat, void *dTar
   elbm_status st = check_box_arg(c, box);
   if (st) return st;
   if (!dFeat || !dTarget || !dScale || !dValid) return fail(c, ELBM_EINVAL, "alpha_samples: NULL output");
+  if (c->P.lattice != ELBM_LATTICE_D3Q19) return fail(c, ELBM_EINVAL, "alpha_samples: the learned starter is D3Q19");
   const Model M = make_model(c->P);
   const dim3 grid(c->nblocks), blk(BLK);
   if (c->P.ncomp == 2) {

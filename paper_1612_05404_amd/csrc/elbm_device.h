@@ -26,6 +26,30 @@ __host__ __device__ constexpr double wgt(int p) {
 }
 __host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
 
+// Lattice descriptors, the template parameter L of every kernel that walks
+// the velocity set.  D3Q19 (the 3-D lift, order in elbm.h) and D2Q9, the
+// paper's own lattice (Sec. II): rest, +x, -x, +y, -y, (+1,+1), (-1,-1),
+// (+1,-1), (-1,+1), weights 4/9, 1/9, 1/36, c_s^2 = 1/3; a D2Q9 box is one
+// x-y plane (nz = 1, bounded in z).  Opposite directions sit at adjacent
+// (odd, even) indices in both, so opp() serves both.
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  __host__ __device__ static constexpr double w(int p) { return wgt(p); }
+};
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int cx[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int cy[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  __host__ __device__ static constexpr double w(int p) {
+    return p == 0 ? 4.0 / 9.0 : (p < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+constexpr int QMAX = 19;
+
 constexpr double CS2 = 1.0 / 3.0;
 
 struct BoxDev {
@@ -72,10 +96,6 @@ struct Ptrs {
   const BoxDev *boxes;
   const int32_t *block_box;
   double *partials;     // [nblocks][4]
-  // node-components whose alpha needs the iteration (screening pass -> Newton pass)
-  int32_t *nl_count;    // entries this step (zeroed by k_density)
-  uint32_t *nl_idx;     // [C N] 2 g + s (one component: g)
-  double *nl_L, *nl_amax, *nl_M2, *nl_a;  // [C N] set-up values; nl_a < 0: learned starter wanted, start -nl_a
   double *res_part;     // [nblocks][2] Poisson residual and max|rhs| per block
   double *fel_part;     // [nblocks][3] electric force summed per block (recorded steps)
   double *scal;         // [nboxes][NSCAL]
@@ -239,10 +259,22 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // Second-order equilibrium (Sec. II, below Eq. lattice-b), with the exact
 // lattice factors 1/c_s^2 = 3 and 1/(2 c_s^4) = 4.5 (no divisions):
 // w rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u].
+// c.u with the lattice vector's components (0 or +-1) folded in: zero
+// components add no term (an FMA with a zero coefficient is not folded away
+// under IEEE rules), unit ones add or subtract.
 template <typename R>
+__device__ __forceinline__ R cdot(int cx, int cy, int cz, R ux, R uy, R uz) {
+  R cu = R(0);
+  bool first = true;
+  if (cx) { cu = cx > 0 ? ux : -ux; first = false; }
+  if (cy) { cu = first ? (cy > 0 ? uy : -uy) : (cy > 0 ? cu + uy : cu - uy); first = false; }
+  if (cz) { cu = first ? (cz > 0 ? uz : -uz) : (cz > 0 ? cu + uz : cu - uz); }
+  return cu;
+}
+template <typename Lat, typename R>
 __device__ __forceinline__ R feq(int p, R rho, R ux, R uy, R uz, R uu) {
-  const R cu = R(kCx[p]) * ux + R(kCy[p]) * uy + R(kCz[p]) * uz;
-  return R(wgt(p)) * rho * (R(1) + R(3) * cu + R(4.5) * (cu * cu) - R(1.5) * uu);
+  const R cu = cdot<R>(Lat::cx[p], Lat::cy[p], Lat::cz[p], ux, uy, uz);
+  return R(Lat::w(p)) * rho * (R(1) + R(3) * cu + R(4.5) * (cu * cu) - R(1.5) * uu);
 }
 
 // 1/d to ~1 ulp: hardware reciprocal estimate refined by two Newton steps.
@@ -284,30 +316,6 @@ __device__ __forceinline__ double log1p_fast(double y) {
   // ln2 split: the high part has 33 significant bits, so de * LN2_HI is exact
   return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * q + c * __builtin_amdgcn_rcp(t)));
 }
-
-// ln(1 + y) for |y| <= 1/4 to ~2 ulp without the range reduction of
-// log1p_fast: ln(1 + y) = 2 atanh(s), s = y / (2 + y) with the rounding error
-// of 2 + y folded in (Fast2Sum, |y| < 2), |s| <= 1/7, summed as
-// 2 s sum_{k=0}^{9} s^2k / (2k + 1) (first dropped term below 1e-18 relative).
-__device__ __forceinline__ double log1p_small(double y) {
-  const double t = 2.0 + y;
-  const double e = (2.0 - t) + y;  // t + e = 2 + y exactly
-  const double r = rcp_nr(t);
-  const double s = (y * r) * fma(-e, r, 1.0);
-  const double s2 = s * s;
-  double q = 1.0 / 19.0;
-  q = fma(q, s2, 1.0 / 17.0);
-  q = fma(q, s2, 1.0 / 15.0);
-  q = fma(q, s2, 1.0 / 13.0);
-  q = fma(q, s2, 1.0 / 11.0);
-  q = fma(q, s2, 1.0 / 9.0);
-  q = fma(q, s2, 1.0 / 7.0);
-  q = fma(q, s2, 1.0 / 5.0);
-  q = fma(q, s2, 1.0 / 3.0);
-  q = fma(q, s2, 1.0);
-  return 2.0 * s * q;
-}
-constexpr double LOG1P_SMALL_MAX = 0.25;
 
 // e^x for |x| < 700 to ~2 ulp: x = k ln2 + r with the same split of ln2 as
 // log1p_fast (k ln2_hi exact), |r| <= ln2/2, e^r by its Taylor series through
@@ -445,22 +453,6 @@ __device__ __forceinline__ double series_dq(double b, const double *M) {
   return h;
 }
 
-// The same truncated series at any degree D (M[k - 2] = M_k, k <= D + 1).
-template <int D>
-__device__ __forceinline__ double series_qd(double b, double L, const double *M) {
-  double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D * (D - 1));
-#pragma unroll
-  for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k * (k - 1)));
-  return fma(b, h, L);
-}
-template <int D>
-__device__ __forceinline__ double series_dqd(double b, const double *M) {
-  double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D);
-#pragma unroll
-  for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k));
-  return h;
-}
-
 // State between the set-up pass and the Newton polish.
 struct AlphaSetup {
   double L, amax, xmax, a;  // a: the starter so far
@@ -469,7 +461,7 @@ struct AlphaSetup {
   bool want_learned;        // the learned starter would be used here
 };
 
-template <typename T>
+template <typename Lat, typename T>
 __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double rho, double ux, double uy,
                                                   double uz, int guess, double rtol) {
   const double uu = ux * ux + uy * uy + uz * uz;
@@ -480,16 +472,16 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
   for (int k = 0; k < SERIES_DEG; ++k) M[k] = 0.0;
   bool nonpos = false;
 #pragma unroll  // fully: the lattice vectors fold into the equilibria (3 % faster than by 4)
-  for (int p = 0; p < NQ; ++p) {
+  for (int p = 0; p < Lat::Q; ++p) {
     const double fp = double(f[p * BLK]);
-    const double wr = wgt(p) * rho;
-    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
+    const double wr = Lat::w(p) * rho;
+    const double d = feq<Lat, double>(p, rho, ux, uy, uz, uu) - fp;
     const double x = d * rcp_nr(fp);
     nonpos |= !(fp > 0.0);
     xs[p * XSTRIDE] = x;
     xmax = fmax(xmax, fabs(x));
     if (x < 0.0) amax = fmin(amax, -rcp_nr(x));
-    L += d * log1p_fast((fp - wr) * (irho * (1.0 / wgt(p))));
+    L += d * log1p_fast((fp - wr) * (irho * (1.0 / Lat::w(p))));
     double t = fp * x * x;
 #pragma unroll
     for (int k = 0; k < SERIES_DEG; ++k) {
@@ -541,115 +533,6 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
   return st;
 }
 
-// The alpha set-up of one node and component from registers (the screening
-// pass of the collision's alpha): the same quantities and decisions as
-// alpha_setup, with x_p held in registers instead of LDS.  Two variants,
-// chosen per wave (every lane takes the same one): the quiet one, for waves
-// whose fluid lanes all have max|x| <= 2.5e-3 and max|y| <= 1/4 with
-// y_p = f_p/(w_p rho) - 1, forms L with log1p_small and the series at
-// degree 6 (there its tail bound still accepts at alpha near 2:
-// (2 max|x|)^5 / 21 < 2.5e-13); the other one with log1p_fast and degree
-// SERIES_DEG.  Either returns a root within the stopping rule.
-template <typename T, int D, bool QUIET>
-__device__ __forceinline__ AlphaSetup alpha_screen_tail(const T (&f)[NQ], const double *xs, double rho,
-                                                        double ux, double uy, double uz, double xmax, double amax,
-                                                        bool nonpos, int guess, double rtol) {
-  // the equilibria and y_p are recomputed here rather than kept from the
-  // first pass (38 + 38 registers): the empty asm hides that rho and u are
-  // the same values, so the compiler cannot carry them over
-  asm volatile("" : "+v"(rho), "+v"(ux), "+v"(uy), "+v"(uz));
-  const double uu = ux * ux + uy * uy + uz * uz;
-  const double irho = rcp_nr(rho);
-  double L = 0.0;
-  double M[D];  // M[k - 2] = M_k, k = 2 .. D + 1
-#pragma unroll
-  for (int k = 0; k < D; ++k) M[k] = 0.0;
-#pragma unroll
-  for (int p = 0; p < NQ; ++p) {
-    const double fp = double(f[p]);
-    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
-    const double y = (fp - wgt(p) * rho) * (irho * (1.0 / wgt(p)));
-    L += d * (QUIET ? log1p_small(y) : log1p_fast(y));
-    const double x = xs[p * XSTRIDE];
-    double t = fp * x * x;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      M[k] += t;
-      t *= x;
-    }
-  }
-  AlphaSetup st;
-  st.M2 = M[0];
-  st.L = L;
-  st.amax = amax;
-  st.xmax = xmax;
-  st.a = 2.0;
-  st.want_learned = false;
-  if (nonpos) {
-    st.state = 2;
-    return st;
-  }
-  if (xmax < 1e-12) {
-    st.state = 1;
-    return st;
-  }
-  st.state = L < 0.0 ? 0 : 2;
-  if (st.state == 0 && (guess == ELBM_GUESS_SERIES || guess == ELBM_GUESS_MLP)) {
-    double b = 2.0;
-#pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
-      const double q = series_qd<D>(b, L, M);
-      const double dq = series_dqd<D>(b, M);
-      if (!(dq > 0.0)) break;
-      b -= q / dq;
-    }
-    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
-      st.a = b;
-      const double bx = b * xmax;
-      if (bx < 0.5) {
-        const double qb = series_qd<D>(b, L, M);
-        double bd = b;  // b^D
-#pragma unroll
-        for (int k = 1; k < D; ++k) bd *= b;
-        const double tail = bd * M[D - 1] / (double((D + 1) * D) * (1.0 - bx));
-        if (b * (fabs(qb) + tail) <= 0.25 * rtol * b * b * M[0] * (1.0 - bx / 3.0)) st.state = 3;
-      }
-    } else {
-      st.want_learned = guess == ELBM_GUESS_MLP;
-    }
-  }
-  return st;
-}
-
-constexpr double QUIET_XMAX = 2.5e-3;
-
-// fl: this lane holds a fluid node (the others take part in the wave-wide
-// choice only).  f: the 19 pulled populations; rho, u: their FP64 moments;
-// xs: the thread's LDS column for x_p (element p at p * XSTRIDE).
-template <typename T>
-__device__ __forceinline__ AlphaSetup alpha_screen(const T (&f)[NQ], double *xs, bool fl, double rho, double ux,
-                                                   double uy, double uz, int guess, double rtol) {
-  const double uu = ux * ux + uy * uy + uz * uz;
-  const double irho = rcp_nr(rho);
-  double xmax = 0.0, xmin = 0.0, ymax = 0.0;
-  bool nonpos = false;
-#pragma unroll
-  for (int p = 0; p < NQ; ++p) {
-    const double fp = double(f[p]);
-    const double d = feq<double>(p, rho, ux, uy, uz, uu) - fp;
-    const double x = d * rcp_nr(fp);
-    xs[p * XSTRIDE] = x;
-    nonpos |= !(fp > 0.0);
-    xmax = fmax(xmax, fabs(x));
-    xmin = fmin(xmin, x);
-    ymax = fmax(ymax, fabs((fp - wgt(p) * rho) * (irho * (1.0 / wgt(p)))));
-  }
-  const double amax = xmin < 0.0 ? -rcp_nr(xmin) : INFINITY;
-  const bool quiet = !fl || (xmax <= QUIET_XMAX && ymax <= LOG1P_SMALL_MAX);
-  if (__all(quiet)) return alpha_screen_tail<T, 6, true>(f, xs, rho, ux, uy, uz, xmax, amax, nonpos, guess, rtol);
-  return alpha_screen_tail<T, SERIES_DEG, false>(f, xs, rho, ux, uy, uz, xmax, amax, nonpos, guess, rtol);
-}
-
 // Newton's starting point for a node that needs the iteration (state 0).
 __device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
   double a = st.a;
@@ -661,11 +544,11 @@ __device__ __forceinline__ double alpha_start(const AlphaSetup &st, double a0) {
 // g at the top of the positivity interval, g(amax-) = sum_p f_p phi(amax x_p)
 // + amax L, where the population that vanishes contributes f_p phi(-1) = f_p:
 // with L < 0 a root exists in (0, amax) iff this is positive.
-template <typename T>
+template <typename Lat, typename T>
 __device__ __forceinline__ double alpha_g_top(const T *f, const double *xs, double L, double amax) {
   double S = 0.0;
 #pragma unroll 1
-  for (int p = 0; p < NQ; ++p) {
+  for (int p = 0; p < Lat::Q; ++p) {
     const double y = amax * xs[p * XSTRIDE];
     S += double(f[p * BLK]) * (y > -1.0 ? phi_of(y, log1p_fast(y)) : 1.0);
   }
@@ -682,7 +565,7 @@ __device__ __forceinline__ double alpha_g_top(const T *f, const double *xs, doub
 // g'' large, h approaches 1 and the unguarded step leaves the interval and
 // cycles.  The Taylor bound that skips the final evaluation holds for
 // Newton steps only.
-template <typename T>
+template <typename Lat, typename T>
 __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, double L, double amax, double M2,
                                                 double a, double rtol, int maxit, int &iters, bool halley) {
   {
@@ -690,7 +573,7 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
     for (int it = 0; it <= maxit; ++it) {
       double S = 0.0, gp = L, gpp = 0.0;
 #pragma unroll 4
-      for (int p = 0; p < NQ; ++p) {
+      for (int p = 0; p < Lat::Q; ++p) {
         const double fp = double(f[p * BLK]);
         const double x = xs[p * XSTRIDE];
         const double y = a * x;
@@ -717,7 +600,7 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
       if (an >= amax) {
         if (!probed) {
           probed = true;
-          if (!(alpha_g_top<T>(f, xs, L, amax) > 0.0)) break;
+          if (!(alpha_g_top<Lat, T>(f, xs, L, amax) > 0.0)) break;
         }
         an = 0.5 * (a + amax);
         newton = false;
@@ -747,7 +630,7 @@ __device__ __forceinline__ double alpha_iterate(const T *f, const double *xs, do
   return fmin(2.0, 0.99 * amax);
 }
 
-template <typename T>
+template <typename Lat, typename T>
 __device__ __forceinline__ double alpha_newton(const T *f, const double *xs, AlphaSetup st, double a0, double rtol,
                                                int maxit, int &iters, bool halley = false) {
   if (st.state == 1 || st.state == 3) {
@@ -755,7 +638,7 @@ __device__ __forceinline__ double alpha_newton(const T *f, const double *xs, Alp
     return st.state == 1 ? 2.0 : st.a;
   }
   if (st.state == 0)
-    return alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), rtol, maxit, iters, halley);
+    return alpha_iterate<Lat, T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), rtol, maxit, iters, halley);
   iters = -1;
   return fmin(2.0, 0.99 * st.amax);
 }

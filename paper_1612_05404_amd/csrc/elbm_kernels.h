@@ -26,15 +26,15 @@ namespace elbm {
 // Neighbour mask of every node (the geometry is fixed once a box is set):
 // bit p set when r + c_p is a solid node or outside a bounded box.  The
 // kernels read it instead of 18 neighbour type bytes.
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_neighbour_mask(Ptrs<T, F> a, uint32_t *nbm) {
   Node nd;
   decode(a, nd);
   if (!nd.live) return;
   uint32_t msk = 0u;
 #pragma unroll
-  for (int p = 1; p < NQ; ++p) {
-    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+  for (int p = 1; p < Lat::Q; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
     if (m < 0 || (a.type[nd.B.off + m] & 3) == K_SOLID) msk |= 1u << p;
   }
   nbm[nd.g] = msk;
@@ -43,21 +43,20 @@ __global__ __launch_bounds__(BLK) void k_neighbour_mask(Ptrs<T, F> a, uint32_t *
 // Streaming (left side of Eq. lattice-b) by pulling + densities and the
 // Shan-Chen pseudo-potential psi = 1 - exp(-rho) (rho_0 = 1).  Sums run in
 // the field type F in the order p = 0..18.
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.nl_count = 0;  // this step's alpha iteration list
   if (!nd.live) return;
   const int k = a.type[nd.g] & 3;
   const uint32_t msk = a.nbm[nd.g];  // the source of p is the neighbour in direction opp(p)
-  int src[NQ];
-  bool bb[NQ];
+  int src[Lat::Q];
+  bool bb[Lat::Q];
   src[0] = nd.n;
   bb[0] = false;
 #pragma unroll
-  for (int p = 1; p < NQ; ++p) {
-    src[p] = nbr(nd.B, nd.x, nd.y, nd.z, -kCx[p], -kCy[p], -kCz[p]);
+  for (int p = 1; p < Lat::Q; ++p) {
+    src[p] = nbr(nd.B, nd.x, nd.y, nd.z, -Lat::cx[p], -Lat::cy[p], -Lat::cz[p]);
     bb[p] = ((msk >> opp(p)) & 1u) || src[p] < 0;
   }
 #pragma unroll
@@ -65,12 +64,12 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
     F r = F(0);
     if (k == K_INLET || k == K_OUTLET) {
 #pragma unroll
-      for (int p = 0; p < NQ; ++p) r += F(a.fa[(int64_t)(s * NQ + p) * a.N + nd.g]);
+      for (int p = 0; p < Lat::Q; ++p) r += F(a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.g]);
     } else if (k == K_FLUID) {
 #pragma unroll
-      for (int p = 0; p < NQ; ++p) {
-        const T v = bb[p] ? a.fa[(int64_t)(s * NQ + opp(p)) * a.N + nd.g]
-                          : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + src[p]];
+      for (int p = 0; p < Lat::Q; ++p) {
+        const T v = bb[p] ? a.fa[(int64_t)(s * Lat::Q + opp(p)) * a.N + nd.g]
+                          : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + src[p]];
         r += F(v);
       }
     }
@@ -82,7 +81,7 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
 // 19-point isotropic gradient G = (1/c_s^2) sum_p w_p c_p rho_A(r + c_p) (a
 // solid or outside neighbour takes the centre value), stored as the unit
 // normal n = G/|G| (0 where |G| <= 1e-12) and |G|^2.
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
@@ -93,14 +92,14 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
     const F c = a.rho[nd.g];
     const uint32_t msk = a.nbm[nd.g];
 #pragma unroll
-    for (int p = 1; p < NQ; ++p) {
-      const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+    for (int p = 1; p < Lat::Q; ++p) {
+      const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
       F v = c;
       if (m >= 0 && !((msk >> p) & 1u)) v = a.rho[nd.B.off + m];
       // zero lattice-vector components add nothing: skipped (same sums)
-      if (kCx[p]) g0 += F(wgt(p) * kCx[p]) * v;
-      if (kCy[p]) g1 += F(wgt(p) * kCy[p]) * v;
-      if (kCz[p]) g2 += F(wgt(p) * kCz[p]) * v;
+      if (Lat::cx[p]) g0 += F(Lat::w(p) * Lat::cx[p]) * v;
+      if (Lat::cy[p]) g1 += F(Lat::w(p) * Lat::cy[p]) * v;
+      if (Lat::cz[p]) g2 += F(Lat::w(p) * Lat::cz[p]) * v;
     }
     g0 /= F(CS2);
     g1 /= F(CS2);
@@ -120,7 +119,7 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
 // normal), smoothed Heaviside theta, the two charge weights of Eqs.
 // surface-q2 / surface-q3 and their per-block sums (all nodes, Poisson-unknown
 // nodes).
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
   Node nd;
   decode(a, nd);
@@ -134,18 +133,18 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
       const uint32_t msk = a.nbm[nd.g];
       F div = F(0);
 #pragma unroll
-      for (int p = 1; p < NQ; ++p) {
-        const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+      for (int p = 1; p < Lat::Q; ++p) {
+        const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
         const bool in = m >= 0 && !((msk >> p) & 1u);
         const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
         // c_p . n(r + c_p): only the nonzero components of c_p (all +-1) are
         // loaded, 30 gathers per node instead of 54; the products are exact,
         // so the sums equal the full three-term ones
         F s = F(-0.0);  // -0 + x == x for every x: the first add folds away
-        if (kCx[p]) s += F(kCx[p]) * (in ? a.grad[gm] : c0);
-        if (kCy[p]) s += F(kCy[p]) * (in ? a.grad[a.N + gm] : c1);
-        if (kCz[p]) s += F(kCz[p]) * (in ? a.grad[2 * a.N + gm] : c2);
-        div += F(wgt(p)) * s;
+        if (Lat::cx[p]) s += F(Lat::cx[p]) * (in ? a.grad[gm] : c0);
+        if (Lat::cy[p]) s += F(Lat::cy[p]) * (in ? a.grad[a.N + gm] : c1);
+        if (Lat::cz[p]) s += F(Lat::cz[p]) * (in ? a.grad[2 * a.N + gm] : c2);
+        div += F(Lat::w(p)) * s;
       }
       const F K = -div / F(CS2);
       const F rA = a.rho[nd.g];
@@ -365,7 +364,7 @@ __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
 
 // |E|^2 with E = E_ext - grad phi (19-point gradient; an outside neighbour
 // takes the centre value, wall nodes carry their fixed potential).
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
   Node nd;
   decode(a, nd);
@@ -374,12 +373,12 @@ __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
   const F c = a.phi[nd.g];
   F g0 = F(0), g1 = F(0), g2 = F(0);
 #pragma unroll
-  for (int p = 1; p < NQ; ++p) {
-    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+  for (int p = 1; p < Lat::Q; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
     const F v = m >= 0 ? a.phi[nd.B.off + m] : c;
-    g0 += F(wgt(p) * kCx[p]) * v;
-    g1 += F(wgt(p) * kCy[p]) * v;
-    g2 += F(wgt(p) * kCz[p]) * v;
+    g0 += F(Lat::w(p) * Lat::cx[p]) * v;
+    g1 += F(Lat::w(p) * Lat::cy[p]) * v;
+    g2 += F(Lat::w(p) * Lat::cz[p]) * v;
   }
   const F e0 = F(nd.B.E[0]) - g0 / F(CS2), e1 = F(nd.B.E[1]) - g1 / F(CS2), e2 = F(nd.B.E[2]) - g2 / F(CS2);
   a.e2[nd.g] = e0 * e0 + e1 * e1 + e2 * e2;
@@ -391,13 +390,13 @@ template <> struct LearnLds<true> { MlpShared net; };
 
 // x_p = (f_eq_p - f_p)/f_p of every direction into the wave's LDS scratch,
 // with the same expression as the alpha set-up pass (bit-identical).
-template <typename T>
+template <typename Lat, typename T>
 __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, double ux, double uy, double uz) {
   const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll 4
-  for (int p = 0; p < NQ; ++p) {
+  for (int p = 0; p < Lat::Q; ++p) {
     const double fp = double(f[p * BLK]);
-    xs[p * XSTRIDE] = (feq<double>(p, rho, ux, uy, uz, uu) - fp) * rcp_nr(fp);
+    xs[p * XSTRIDE] = (feq<Lat, double>(p, rho, ux, uy, uz, uu) - fp) * rcp_nr(fp);
   }
 }
 
@@ -406,18 +405,18 @@ __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, dou
 // f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted mean density of its
 // fluid neighbours (rho_in when it has none).  Written to the output buffer,
 // which the next step pulls from.
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 __device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M, const Node &nd) {
   double sw = 0.0, sr[C];
 #pragma unroll
   for (int s = 0; s < C; ++s) sr[s] = 0.0;
 #pragma unroll 1
-  for (int p = 1; p < NQ; ++p) {
-    const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+  for (int p = 1; p < Lat::Q; ++p) {
+    const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
     if (m < 0 || (a.type[nd.B.off + m] & 3) != K_FLUID) continue;
-    sw += wgt(p);
+    sw += Lat::w(p);
 #pragma unroll
-    for (int s = 0; s < C; ++s) sr[s] += wgt(p) * double(a.rho[(int64_t)s * a.N + nd.B.off + m]);
+    for (int s = 0; s < C; ++s) sr[s] += Lat::w(p) * double(a.rho[(int64_t)s * a.N + nd.B.off + m]);
   }
   const double ux = double(a.ubc[nd.g]), uy = double(a.ubc[a.N + nd.g]), uz = double(a.ubc[2 * a.N + nd.g]);
   const double uu = ux * ux + uy * uy + uz * uz;
@@ -425,23 +424,9 @@ __device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M,
   for (int s = 0; s < C; ++s) {
     const double r = sw > 0.0 ? sr[s] / sw : M.rho_in[s];
 #pragma unroll 1
-    for (int p = 0; p < NQ; ++p) a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = T(feq<double>(p, r, ux, uy, uz, uu));
+    for (int p = 0; p < Lat::Q; ++p) a.fb[(int64_t)(s * Lat::Q + p) * a.N + nd.g] = T(feq<Lat, double>(p, r, ux, uy, uz, uu));
   }
 }
-
-// The collision (Eq. lattice-b) in three kernels.  The entropic alpha (Eq.
-// entropic) and the Carreau viscosity depend only on the pulled populations,
-// not on the forces, so the alpha kernels need nothing of the step's field
-// chain (densities, charge, Poisson, E) and run beside it on a second stream;
-// they leave alpha * beta per node and component.  k_collide then adds the
-// forces and writes the post-collision populations.
-//
-// k_alpha screens every node: its set-up (moments, x_p, L, the series root
-// and its bound) decides most nodes at once -- at equilibrium, a series root
-// the bound accepts, or no root (fallback) -- and it finishes those with the
-// viscosity.  The others (the iteration is needed) go on a device list, which
-// k_alpha_newton works through densely: full waves of nodes that iterate,
-// the learned starter's matrix-core inference on whole waves.
 
 // Carreau viscosity (Eqs. strain2, carreau) of one component from the
 // components of its non-equilibrium stress Pi = sum_p (f_p - f_eq_p) c_p c_p,
@@ -457,262 +442,153 @@ __device__ __forceinline__ double viscosity(const Model &M, double nflow, double
   return double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow1p<R>(lg * lg, R(0.5) * (nf - R(1))));
 }
 
-// Per-wave counters of the alpha kernels added to the boxes' counters: one
-// atomic per wave and counter when the wave's active lanes share a box.
-__device__ __forceinline__ void alpha_counters(unsigned long long *cnt, uint32_t *err, const Model &M, bool act,
-                                               int bb, unsigned long long c_fb, unsigned long long c_it,
-                                               unsigned long long c_col) {
-  const unsigned long long am = __ballot(act);
-  if (!am) return;
-  const int lane = threadIdx.x & 63;
-  const int first = __ffsll((long long)am) - 1;
-  const int bb0 = __shfl(bb, first, 64);
-  if (__all(!act || bb == bb0)) {
-    c_fb = wave_sum_u64(c_fb);
-    c_it = wave_sum_u64(c_it);
-    c_col = wave_sum_u64(c_col);
-    if (lane == first) {
-      unsigned long long *cn = cnt + (int64_t)bb0 * NCNT;
-      if (c_fb) atomicAdd(cn + 0, c_fb);
-      if (c_it) atomicAdd(cn + 1, c_it);
-      if (c_col) atomicAdd(cn + 4, c_col);
-      if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(err, ERR_ALPHA);
-    }
-  } else if (act) {
-    unsigned long long *cn = cnt + (int64_t)bb * NCNT;
-    if (c_fb) atomicAdd(cn + 0, c_fb);
-    if (c_it) atomicAdd(cn + 1, c_it);
-    if (c_col) atomicAdd(cn + 4, c_col);
-    if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(err, ERR_ALPHA);
-  }
-}
+// The collision (Eq. lattice-b) in two kernels.  The entropic alpha (Eq.
+// entropic) and the Carreau viscosity depend only on the pulled populations,
+// not on the forces, so k_alpha needs nothing of the step's field chain
+// (densities, charge, Poisson, E) and runs beside it on a second stream; it
+// leaves alpha * beta per node and component.  k_collide then adds the forces
+// and writes the post-collision populations.
 
-// k_alpha (screening pass): one thread per fluid node and component (the
-// component is the grid's y index): the 19 pulled populations in registers,
-// their FP64 moments and the alpha set-up (alpha_screen).  Decided nodes get
-// alpha, the viscosity and alpha * beta; the rest are appended to the
-// iteration list (one atomic per wave).
-template <typename T, typename F, int C>
-__global__ __launch_bounds__(BLK, 2) void k_alpha(Ptrs<T, F> a, Model M, int record) {
-  __shared__ __align__(16) double lds_x[NQ * BLK];  // x_p per thread: column p * 64 + lane of its wave
+// k_alpha: for each fluid node and component, pull the 19 populations and
+// their FP64 moments, (LEARN) run the learned starter over the wave, solve
+// alpha in FP64, evaluate the viscosity, store ab = alpha c_s^2/(2 nu + c_s^2).
+// Per-lane work is predicated on `fl` so that the matrix-core section runs on
+// whole waves.  With FP32 populations two blocks fit a CU's LDS: the register
+// budget is held to two waves per SIMD (matrix accumulators included).
+template <typename Lat, typename T, typename F, int C, bool LEARN>
+__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F> a, Model M, MlpDev W, int record) {
+  // thread-private LDS: populations of the current component (column p * BLK
+  // + tid) and, per wave, x_p (column p * 64 + lane), whose 9.5 KB also hold
+  // the starter's two [64][32] bf16 tiles before the alpha solve
+  __shared__ T lds_f[Lat::Q * BLK];
+  __shared__ __align__(16) double lds_x[Lat::Q * BLK];
+  __shared__ __align__(16) LearnLds<LEARN> learn;
+  if constexpr (LEARN) mlp_stage(W, learn.net);
   Node nd;
   if (a.tx) decode_tile(a, nd);
   else decode(a, nd);
-  const int s = C == 2 ? (int)blockIdx.y : 0;
-  const int lane = threadIdx.x & 63;
-  unsigned long long c_fb = 0, c_col = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned long long c_fb = 0, c_it = 0, c_col = 0;
   const int k = nd.live ? (a.type[nd.g] & 3) : K_SOLID;
   const bool fl = nd.live && k == K_FLUID;
-  const uint32_t solid = fl ? a.nbm[nd.g] : 0u;  // neighbour p solid or outside (bit p)
-  // ---- pulled populations and their moments, summed in FP64 whatever the
-  // storage: the equilibrium of the alpha solve must carry exactly the
-  // density and momentum of f (sum Delta = 0), or the rounding of an FP32
-  // sum swamps the O(|Delta|^2) entropy balance.
-  T f[NQ];
-  double dr = 1.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  int nl[Lat::Q];
+  unsigned solid = 0u;
   if (fl) {
-    dr = 0.0;
+    // ---- neighbours: local index, solid-or-outside flag
+    nl[0] = nd.n;
+    solid = a.nbm[nd.g];
 #pragma unroll
-    for (int p = 0; p < NQ; ++p) {
-      const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
-      const bool bounce = (p != 0) && ((solid >> q) & 1u);
-      const int m = p ? nbr(nd.B, nd.x, nd.y, nd.z, kCx[q], kCy[q], kCz[q]) : nd.n;
-      f[p] = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g] : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + m];
-      const double dv = double(f[p]);
-      dr += dv;
-      jx += double(kCx[p]) * dv;
-      jy += double(kCy[p]) * dv;
-      jz += double(kCz[p]) * dv;
-    }
-  } else {
-#pragma unroll
-    for (int p = 0; p < NQ; ++p) f[p] = T(wgt(p));
-  }
-  const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
-  double *xs = lds_x + (threadIdx.x >> 6) * (NQ * 64) + lane;
-  const AlphaSetup st = alpha_screen<T>(f, xs, fl, dr, ux, uy, uz, M.alpha_guess, M.rtol);
-  const bool need = fl && st.state == 0;
-  if (fl && !need) {
-    const double al = st.state == 1 ? 2.0 : st.state == 3 ? st.a : fmin(2.0, 0.99 * st.amax);
-    const int its = st.state == 2 ? -1 : 0;
-    c_col = 1;
-    if (its < 0) c_fb = 1;
-    double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (M.carreau) {
-      // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
-      // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
-#pragma unroll
-      for (int p = 0; p < NQ; ++p) {
-        const double d = double(f[p]);
-        P[0] += d * double(kCx[p] * kCx[p]);
-        P[1] += d * double(kCy[p] * kCy[p]);
-        P[2] += d * double(kCz[p] * kCz[p]);
-        P[3] += d * double(kCx[p] * kCy[p]);
-        P[4] += d * double(kCx[p] * kCz[p]);
-        P[5] += d * double(kCy[p] * kCz[p]);
-      }
-      P[0] -= dr * (CS2 + ux * ux);
-      P[1] -= dr * (CS2 + uy * uy);
-      P[2] -= dr * (CS2 + uz * uz);
-      P[3] -= dr * (ux * uy);
-      P[4] -= dr * (ux * uz);
-      P[5] -= dr * (uy * uz);
-    }
-    const double nu = viscosity<F>(M, nd.B.n_flow, P[0], P[1], P[2], P[3], P[4], P[5], dr, al);
-    a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
-    if (record) {
-      a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
-      a.rec_iters[(int64_t)s * a.N + nd.g] = its;
-    }
-  } else if (nd.live && record && !fl) {
-    a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
-    a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
-  }
-  // ---- append the nodes that iterate: one atomic per wave
-  const unsigned long long bal = __ballot(need);
-  if (bal) {
-    const int first = __ffsll((long long)bal) - 1;
-    int base = 0;
-    if (lane == first) base = atomicAdd(a.nl_count, (int)__popcll(bal));
-    base = __shfl(base, first, 64);
-    if (need) {
-      const int i = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
-      a.nl_idx[i] = (uint32_t)(C == 2 ? 2 * nd.g + s : nd.g);
-      a.nl_L[i] = st.L;
-      a.nl_amax[i] = st.amax;
-      a.nl_M2[i] = st.M2;
-      a.nl_a[i] = st.want_learned ? -st.a : st.a;
+    for (int p = 1; p < Lat::Q; ++p) {
+      nl[p] = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
+      if (nl[p] < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
     }
   }
-  alpha_counters(a.cnt, a.err, M, nd.live, nd.bb, c_fb, 0ull, c_col);
-}
-
-// Blocks of the iteration pass: a fixed grid (two blocks per CU fit its
-// LDS) that works through the list in block-sized chunks.
-constexpr int NL_GRID = 512;
-
-// k_alpha_newton (iteration pass): per list entry the node's populations
-// again (pulled as in k_alpha, kept in a thread-private LDS column), x_p,
-// (LEARN) the learned starter for entries whose series root was rejected,
-// Newton (or Halley) from the starter to the stopping rule, the viscosity
-// and alpha * beta.  Whole blocks walk the list together, so the matrix-core
-// section runs on whole waves (lanes past the end carry no features).
-template <typename T, typename F, int C, bool LEARN>
-__global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha_newton(Ptrs<T, F> a, Model M, MlpDev W,
-                                                                             int record) {
-  // thread-private LDS: populations (column p * BLK + tid) and, per wave,
-  // x_p (column p * 64 + lane), whose 9.5 KB also hold the starter's two
-  // [64][32] bf16 tiles before the alpha solve
-  __shared__ T lds_f[NQ * BLK];
-  __shared__ __align__(16) double lds_x[NQ * BLK];
-  __shared__ __align__(16) LearnLds<LEARN> learn;
-  if constexpr (LEARN) mlp_stage(W, learn.net);
-  const int count = *a.nl_count;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   T *f = lds_f + threadIdx.x;
-  double *xs = lds_x + wv * (NQ * 64) + lane;
-  const bool halley = M.alpha_iter == ELBM_ITER_HALLEY;
-  for (int base = blockIdx.x * BLK; base < count; base += gridDim.x * BLK) {
-    const int i = base + threadIdx.x;
-    const bool act = i < count;
-    int64_t g = 0;
-    int s = 0, bb = -1;
-    BoxDev B;
-    int x = 0, y = 0, z = 0, n = 0;
+  double *xs = lds_x + wv * (Lat::Q * 64) + lane;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    // ---- pulled populations and their moments.  The moments are summed in
+    // FP64 whatever the storage: the equilibrium of the alpha solve must carry
+    // exactly the density and momentum of f (sum Delta = 0), or the rounding
+    // of an FP32 sum swamps the O(|Delta|^2) entropy balance.
     double dr = 1.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    AlphaSetup st{};
-    if (act) {
-      const uint32_t code = a.nl_idx[i];
-      g = C == 2 ? (int64_t)(code >> 1) : (int64_t)code;
-      s = C == 2 ? (int)(code & 1u) : 0;
-      bb = a.block_box[g / BLK];  // 256-node blocks never straddle a box
-      B = a.boxes[bb];
-      n = (int)(g - B.off);
-      x = n % B.nx;
-      const int r = n / B.nx;
-      y = r % B.ny;
-      z = r / B.ny;
-      const uint32_t solid = a.nbm[g];
+    if (fl) {
       dr = 0.0;
 #pragma unroll
-      for (int p = 0; p < NQ; ++p) {
-        const int q = opp(p);
+      for (int p = 0; p < Lat::Q; ++p) {
+        const int q = opp(p);  // the source r - c_p is the neighbour in direction opp(p)
         const bool bounce = (p != 0) && ((solid >> q) & 1u);
-        const int m = p ? nbr(B, x, y, z, kCx[q], kCy[q], kCz[q]) : n;
-        const T v = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + g] : a.fa[(int64_t)(s * NQ + p) * a.N + B.off + m];
+        const T v = bounce ? a.fa[(int64_t)(s * Lat::Q + q) * a.N + nd.g]
+                           : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + nl[q]];
         f[p * BLK] = v;
         const double dv = double(v);
         dr += dv;
-        jx += double(kCx[p]) * dv;
-        jy += double(kCy[p]) * dv;
-        jz += double(kCz[p]) * dv;
+        jx += double(Lat::cx[p]) * dv;
+        jy += double(Lat::cy[p]) * dv;
+        jz += double(Lat::cz[p]) * dv;
       }
-      st.L = a.nl_L[i];
-      st.amax = a.nl_amax[i];
-      st.M2 = a.nl_M2[i];
-      const double sa = a.nl_a[i];
-      st.a = fabs(sa);
-      st.want_learned = sa < 0.0;
-      st.state = 0;
     }
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
-    if (act) refill_x<T>(f, xs, dr, ux, uy, uz);
+    // ---- alpha set-up at the component's own velocity (FP64)
+    AlphaSetup st{};
+    if (fl) st = alpha_setup<Lat, T>(f, xs, dr, ux, uy, uz, M.alpha_guess, M.rtol);
     double a0 = 2.0;
     if constexpr (LEARN) {
-      // ---- learned starter on the matrix cores, for waves holding an entry
-      // whose series root was rejected.  Its bf16 tiles overlay the wave's x
-      // scratch, which is refilled afterwards.
-      const bool want = act && st.want_learned;
+      // ---- learned starter on the matrix cores, for waves holding a node
+      // where the series starter was rejected.  Its bf16 tiles overlay the
+      // wave's x scratch, which is refilled afterwards.
+      const bool want = fl && st.want_learned;
       if (__ballot(want) != 0) {
-        float zf[MLP_IN];
+        float z[MLP_IN];
         double sc = 0.0;
         bool valid = false;
-        if (want) valid = features_from_x(xs, zf, sc);
-        zf[NQ] = float(sc);
+        if (want) valid = features_from_x(xs, z, sc);
+        z[Lat::Q] = float(sc);
         wave_sync();
-        __bf16 *tile = reinterpret_cast<__bf16 *>(lds_x + wv * (NQ * 64));
-        put_features(tile, lane, zf, valid);
-        const float yv = mlp_forward_wave(learn.net, tile, tile + 64 * 32, lane);
-        if (valid) a0 = 2.0 + sc * double(yv);
-        wave_sync();
-        if (act) refill_x<T>(f, xs, dr, ux, uy, uz);
+        __bf16 *tile = reinterpret_cast<__bf16 *>(lds_x + wv * (Lat::Q * 64));
+        put_features(tile, lane, z, valid);
+        const float y = mlp_forward_wave(learn.net, tile, tile + 64 * 32, lane);
+        if (valid) a0 = 2.0 + sc * double(y);
+        if (fl) refill_x<Lat, T>(f, xs, dr, ux, uy, uz);
       }
     }
-    unsigned long long c_fb = 0, c_it = 0, c_col = 0;
-    if (act) {
+    if (fl) {
+      // ---- alpha: Newton polish from the starter
+      const double uu = ux * ux + uy * uy + uz * uz;
       int its;
-      const double al = alpha_iterate<T>(f, xs, st.L, st.amax, st.M2, alpha_start(st, a0), M.rtol, M.newton_max,
-                                         its, halley);
-      c_col = 1;
-      if (its < 0) c_fb = 1;
-      else c_it = (unsigned long long)its;
-      double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      const double al = alpha_newton<Lat, T>(f, xs, st, a0, M.rtol, M.newton_max, its, M.alpha_iter == ELBM_ITER_HALLEY);
+      c_col += 1;
+      if (its < 0) c_fb += 1; else c_it += (unsigned long long)its;
+      // ---- viscosity: Newtonian nu0, or Carreau from the shear-rate root,
+      // evaluated in the field precision
+      using R = F;
+      double nu = M.nu0;
       if (M.carreau) {
+        // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
+        // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
+        double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
 #pragma unroll 1
-        for (int p = 0; p < NQ; ++p) {
+        for (int p = 0; p < Lat::Q; ++p) {
           const double d = double(f[p * BLK]);
-          P[0] += d * double(kCx[p] * kCx[p]);
-          P[1] += d * double(kCy[p] * kCy[p]);
-          P[2] += d * double(kCz[p] * kCz[p]);
-          P[3] += d * double(kCx[p] * kCy[p]);
-          P[4] += d * double(kCx[p] * kCz[p]);
-          P[5] += d * double(kCy[p] * kCz[p]);
+          P00 += d * double(Lat::cx[p] * Lat::cx[p]);
+          P11 += d * double(Lat::cy[p] * Lat::cy[p]);
+          P22 += d * double(Lat::cz[p] * Lat::cz[p]);
+          P01 += d * double(Lat::cx[p] * Lat::cy[p]);
+          P02 += d * double(Lat::cx[p] * Lat::cz[p]);
+          P12 += d * double(Lat::cy[p] * Lat::cz[p]);
         }
-        P[0] -= dr * (CS2 + ux * ux);
-        P[1] -= dr * (CS2 + uy * uy);
-        P[2] -= dr * (CS2 + uz * uz);
-        P[3] -= dr * (ux * uy);
-        P[4] -= dr * (ux * uz);
-        P[5] -= dr * (uy * uz);
+        P00 -= dr * (CS2 + ux * ux);
+        P11 -= dr * (CS2 + uy * uy);
+        P22 -= dr * (CS2 + uz * uz);
+        P01 -= dr * (ux * uy);
+        P02 -= dr * (ux * uz);
+        P12 -= dr * (uy * uz);
+        const R Pn = sym3_norm2<R>(R(P00), R(P11), R(P22), R(P01), R(P02), R(P12));
+        const R nf = R(nd.B.n_flow);
+        const R gd = shear_rate<R>(Pn, R(dr), R(al), R(M.nu0), R(M.nu_inf), R(M.lam), nf);
+        const R lg = R(M.lam) * gd;
+        nu = double(R(M.nu_inf) + (R(M.nu0) - R(M.nu_inf)) * pow1p<R>(lg * lg, R(0.5) * (nf - R(1))));
       }
-      const double nu = viscosity<F>(M, B.n_flow, P[0], P[1], P[2], P[3], P[4], P[5], dr, al);
-      a.ab[(int64_t)s * a.N + g] = al * (CS2 / (2.0 * nu + CS2));
+      a.ab[(int64_t)s * a.N + nd.g] = al * (CS2 / (2.0 * nu + CS2));
       if (record) {
-        a.rec_alpha[(int64_t)s * a.N + g] = al;
-        a.rec_iters[(int64_t)s * a.N + g] = its;
+        a.rec_alpha[(int64_t)s * a.N + nd.g] = al;
+        a.rec_iters[(int64_t)s * a.N + nd.g] = its;
       }
+    } else if (nd.live && record) {
+      a.rec_alpha[(int64_t)s * a.N + nd.g] = 0.0;
+      a.rec_iters[(int64_t)s * a.N + nd.g] = 0;
     }
-    alpha_counters(a.cnt, a.err, M, act, bb, c_fb, c_it, c_col);
+  }
+  // ---- counters: wave sums, one atomic per wave and counter
+  c_fb = wave_sum_u64(c_fb);
+  c_it = wave_sum_u64(c_it);
+  c_col = wave_sum_u64(c_col);
+  if (lane == 0) {
+    unsigned long long *cn = a.cnt + (int64_t)nd.bb * NCNT;
+    if (c_fb) atomicAdd(cn + 0, c_fb);
+    if (c_it) atomicAdd(cn + 1, c_it);
+    if (c_col) atomicAdd(cn + 4, c_col);
+    if (c_fb && (M.strict & ELBM_STRICT_ALPHA)) atomicOr(a.err, ERR_ALPHA);
   }
 }
 
@@ -722,7 +598,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha_newton(Pt
 //   f* = f + ab (f_eq - f) + f_eq(rho, u + F/rho) - f_eq(rho, u)
 // (exact-difference source, Eq. add).  Inlet nodes are reset; the recorded
 // half-step velocity is stored on request.
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int record) {
   Node nd;
   decode(a, nd);
@@ -739,14 +615,14 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     F gp[3] = {F(0), F(0), F(0)}, ge[3] = {F(0), F(0), F(0)};
     const F phic = a.phi[nd.g], e2c = a.e2[nd.g];
 #pragma unroll
-    for (int p = 1; p < NQ; ++p) {
-      const int m = nbr(nd.B, nd.x, nd.y, nd.z, kCx[p], kCy[p], kCz[p]);
+    for (int p = 1; p < Lat::Q; ++p) {
+      const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
       const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
       if (m < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
       if ((solid >> p) & 1u) {
-        wall[0] += F(wgt(p) * kCx[p]);
-        wall[1] += F(wgt(p) * kCy[p]);
-        wall[2] += F(wgt(p) * kCz[p]);
+        wall[0] += F(Lat::w(p) * Lat::cx[p]);
+        wall[1] += F(Lat::w(p) * Lat::cy[p]);
+        wall[2] += F(Lat::w(p) * Lat::cz[p]);
       } else {
         F ps[C];
 #pragma unroll
@@ -756,19 +632,19 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
           F sp = F(0);
 #pragma unroll
           for (int t = 0; t < C; ++t) sp += F(M.G[s][t]) * ps[t];
-          acc[s][0] += F(wgt(p)) * sp * F(kCx[p]);
-          acc[s][1] += F(wgt(p)) * sp * F(kCy[p]);
-          acc[s][2] += F(wgt(p)) * sp * F(kCz[p]);
+          acc[s][0] += F(Lat::w(p)) * sp * F(Lat::cx[p]);
+          acc[s][1] += F(Lat::w(p)) * sp * F(Lat::cy[p]);
+          acc[s][2] += F(Lat::w(p)) * sp * F(Lat::cz[p]);
         }
       }
       const F vp = m >= 0 ? a.phi[gm] : phic;
       const F ve = m >= 0 ? a.e2[gm] : e2c;
-      gp[0] += F(wgt(p) * kCx[p]) * vp;
-      gp[1] += F(wgt(p) * kCy[p]) * vp;
-      gp[2] += F(wgt(p) * kCz[p]) * vp;
-      ge[0] += F(wgt(p) * kCx[p]) * ve;
-      ge[1] += F(wgt(p) * kCy[p]) * ve;
-      ge[2] += F(wgt(p) * kCz[p]) * ve;
+      gp[0] += F(Lat::w(p) * Lat::cx[p]) * vp;
+      gp[1] += F(Lat::w(p) * Lat::cy[p]) * vp;
+      gp[2] += F(Lat::w(p) * Lat::cz[p]) * vp;
+      ge[0] += F(Lat::w(p) * Lat::cx[p]) * ve;
+      ge[1] += F(Lat::w(p) * Lat::cy[p]) * ve;
+      ge[2] += F(Lat::w(p) * Lat::cz[p]) * ve;
     }
     const F qn = a.q[nd.g];
     const F rA = a.rho[nd.g];
@@ -787,20 +663,20 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
   for (int s = 0; s < C; ++s) {
     if (!fl) continue;
     // ---- pulled populations and their FP64 moments (as in k_alpha)
-    T f[NQ];
+    T f[Lat::Q];
     double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
-    for (int p = 0; p < NQ; ++p) {
+    for (int p = 0; p < Lat::Q; ++p) {
       const int q = opp(p);
       const bool bounce = (p != 0) && ((solid >> q) & 1u);
-      const int m = p ? nbr(nd.B, nd.x, nd.y, nd.z, kCx[q], kCy[q], kCz[q]) : nd.n;
-      f[p] = bounce ? a.fa[(int64_t)(s * NQ + q) * a.N + nd.g]
-                    : a.fa[(int64_t)(s * NQ + p) * a.N + nd.B.off + m];
+      const int m = p ? nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[q], Lat::cy[q], Lat::cz[q]) : nd.n;
+      f[p] = bounce ? a.fa[(int64_t)(s * Lat::Q + q) * a.N + nd.g]
+                    : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + m];
       const double dv = double(f[p]);
       dr += dv;
-      jx += double(kCx[p]) * dv;
-      jy += double(kCy[p]) * dv;
-      jz += double(kCz[p]) * dv;
+      jx += double(Lat::cx[p]) * dv;
+      jy += double(Lat::cy[p]) * dv;
+      jz += double(Lat::cz[p]) * dv;
     }
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
     const double uu = ux * ux + uy * uy + uz * uz;
@@ -823,17 +699,17 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     const double sx = 2.0 * ux + dx_, sy = 2.0 * uy + dy_, sz = 2.0 * uz + dz_;
     const double ds = dx_ * sx + dy_ * sy + dz_ * sz;
 #pragma unroll
-    for (int p = 0; p < NQ; ++p) {
-      const double fe = feq<double>(p, dr, ux, uy, uz, uu);
-      const double cd = double(kCx[p]) * dx_ + double(kCy[p]) * dy_ + double(kCz[p]) * dz_;
-      const double cs = double(kCx[p]) * sx + double(kCy[p]) * sy + double(kCz[p]) * sz;
-      const double src = wgt(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
+    for (int p = 0; p < Lat::Q; ++p) {
+      const double fe = feq<Lat, double>(p, dr, ux, uy, uz, uu);
+      const double cd = double(Lat::cx[p]) * dx_ + double(Lat::cy[p]) * dy_ + double(Lat::cz[p]) * dz_;
+      const double cs = double(Lat::cx[p]) * sx + double(Lat::cy[p]) * sy + double(Lat::cz[p]) * sz;
+      const double src = Lat::w(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
       const double fp = double(f[p]);
       const double v = fp + ab * (fe - fp) + src;
       const T tv = T(v);
       if (!isfinite(tv)) c_nf += 1;
       else if (tv < T(0)) c_neg += 1;
-      a.fb[(int64_t)(s * NQ + p) * a.N + nd.g] = tv;
+      a.fb[(int64_t)(s * Lat::Q + p) * a.N + nd.g] = tv;
     }
   }
   if (fl && record) {
@@ -847,19 +723,19 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
 #pragma unroll
       for (int s = 0; s < C; ++s)
 #pragma unroll
-        for (int p = 0; p < NQ; ++p) {
-          const double v = double(a.fa[(int64_t)(s * NQ + p) * a.N + nd.g]);
+        for (int p = 0; p < Lat::Q; ++p) {
+          const double v = double(a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.g]);
           r += v;
-          m0 += double(kCx[p]) * v;
-          m1 += double(kCy[p]) * v;
-          m2 += double(kCz[p]) * v;
+          m0 += double(Lat::cx[p]) * v;
+          m1 += double(Lat::cy[p]) * v;
+          m2 += double(Lat::cz[p]) * v;
         }
     }
     a.rec_u[nd.g] = r > 0.0 ? F(m0 / r) : F(0);
     a.rec_u[a.N + nd.g] = r > 0.0 ? F(m1 / r) : F(0);
     a.rec_u[2 * a.N + nd.g] = r > 0.0 ? F(m2 / r) : F(0);
   }
-  if (nd.live && k == K_INLET) inlet_store<T, F, C>(a, M, nd);
+  if (nd.live && k == K_INLET) inlet_store<Lat, T, F, C>(a, M, nd);
   // ---- recorded steps: the electric force summed per block (fixed order)
   if (record) {
     double fe[3] = {double(Fel[0]), double(Fel[1]), double(Fel[2])};
@@ -922,11 +798,11 @@ __global__ __launch_bounds__(BLK) void k_alpha_samples(Ptrs<T, F> a, Model M, in
         jz += double(kCz[p]) * dv;
       }
       const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
-      learned = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_MLP, M.rtol).want_learned;
+      learned = alpha_setup<D3Q19, T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_MLP, M.rtol).want_learned;
       ok = features_from_x(xs, z, sc);
-      const AlphaSetup plain = alpha_setup<T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_STANDARD, M.rtol);
+      const AlphaSetup plain = alpha_setup<D3Q19, T>(f, xs, dr, ux, uy, uz, ELBM_GUESS_STANDARD, M.rtol);
       int its;  // the target: Newton from 2
-      al = alpha_newton<T>(f, xs, plain, 2.0, M.rtol, M.newton_max, its);
+      al = alpha_newton<D3Q19, T>(f, xs, plain, 2.0, M.rtol, M.newton_max, its);
       ok = ok && its >= 0;
     }
 #pragma unroll
@@ -941,7 +817,7 @@ __global__ __launch_bounds__(BLK) void k_alpha_samples(Ptrs<T, F> a, Model M, in
 // ------------------------------------------------------ init / transfer
 // Initial populations of direction p of component s for one box.  Staged
 // host planes are `ps` doubles apart (the largest box size).
-template <typename T, typename F>
+template <typename Lat, typename T, typename F>
 __global__ __launch_bounds__(BLK) void k_init_dir(Ptrs<T, F> a, Model M, int box, int s, int p,
                                                   const double *rho0, const double *u0,
                                                   const double *ubc, const double *xi, double amp,
@@ -954,16 +830,16 @@ __global__ __launch_bounds__(BLK) void k_init_dir(Ptrs<T, F> a, Model M, int box
   double v = 0.0;
   if (k == K_FLUID) {
     const double ux = u0[n], uy = u0[ps + n], uz = u0[2 * ps + n];
-    v = feq<double>(p, rho0[s * ps + n], ux, uy, uz, ux * ux + uy * uy + uz * uz);
+    v = feq<Lat, double>(p, rho0[s * ps + n], ux, uy, uz, ux * ux + uy * uy + uz * uz);
     if (xi) v = v * (1.0 + amp * xi[n]);
   } else if (k == K_INLET) {
     const double ux = ubc ? ubc[n] : 0.0, uy = ubc ? ubc[ps + n] : 0.0, uz = ubc ? ubc[2 * ps + n] : 0.0;
-    v = feq<double>(p, M.rho_in[s], ux, uy, uz, ux * ux + uy * uy + uz * uz);
+    v = feq<Lat, double>(p, M.rho_in[s], ux, uy, uz, ux * ux + uy * uy + uz * uz);
   } else if (k == K_OUTLET) {
-    v = feq<double>(p, M.rho_out[s], 0.0, 0.0, 0.0, 0.0);
+    v = feq<Lat, double>(p, M.rho_out[s], 0.0, 0.0, 0.0, 0.0);
   }
-  a.fa[(int64_t)(s * NQ + p) * a.N + g] = T(v);
-  a.fb[(int64_t)(s * NQ + p) * a.N + g] = T(v);
+  a.fa[(int64_t)(s * Lat::Q + p) * a.N + g] = T(v);
+  a.fb[(int64_t)(s * Lat::Q + p) * a.N + g] = T(v);
 }
 
 template <typename X>
@@ -985,7 +861,7 @@ __global__ __launch_bounds__(BLK) void k_from_double(const double *src, X *dst, 
 // component) pairs of the last recorded step the sum and count of alpha,
 // -min alpha and max alpha (maxima of non-negative values: alpha > 0).
 constexpr int DIAG_W = 9;
-template <typename T, typename F, int C>
+template <typename Lat, typename T, typename F, int C>
 __global__ __launch_bounds__(BLK) void k_diag(Ptrs<T, F> a, int box, double *out) {
   const BoxDev B = a.boxes[box];
   const int n = blockIdx.x * BLK + threadIdx.x;
@@ -996,12 +872,12 @@ __global__ __launch_bounds__(BLK) void k_diag(Ptrs<T, F> a, int box, double *out
 #pragma unroll
     for (int s = 0; s < C; ++s)
 #pragma unroll
-      for (int p = 0; p < NQ; ++p) {
-        const double f = double(a.fa[(int64_t)(s * NQ + p) * a.N + g]);
+      for (int p = 0; p < Lat::Q; ++p) {
+        const double f = double(a.fa[(int64_t)(s * Lat::Q + p) * a.N + g]);
         v[s] += f;
-        v[2] += kCx[p] * f;
-        v[3] += kCy[p] * f;
-        v[4] += kCz[p] * f;
+        v[2] += Lat::cx[p] * f;
+        v[3] += Lat::cy[p] * f;
+        v[4] += Lat::cz[p] * f;
       }
     if ((a.type[g] & 3) == K_FLUID)
 #pragma unroll

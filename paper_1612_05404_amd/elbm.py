@@ -45,6 +45,7 @@ class elbm_params(ct.Structure):
         ("rho_th", ct.c_double), ("w_theta", ct.c_double), ("xi_b", ct.c_double), ("xi_s", ct.c_double),
         ("newton_rtol", ct.c_double), ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
         ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("alpha_iter", ct.c_int32),
+        ("lattice", ct.c_int32), ("pad2_", ct.c_int32),
     ]
 
 
@@ -86,7 +87,7 @@ TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
-ABI_VERSION = 4  # include/elbm.h ELBM_ABI_VERSION
+ABI_VERSION = 5  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -156,6 +157,7 @@ def make_params(p, storage: int, guess: int = 0, alpha_iter: int = 0, strict: in
     P.strict = int(strict)
     P.sor_tol = float(getattr(p, "sor_tol", 0.0))
     P.sor_check_every = int(getattr(p, "sor_check_every", 0))
+    P.lattice = int(getattr(p, "lattice", 0))
     gw = p.G if p.Gw is None else p.Gw
     for s in range(2):
         for t in range(2):
@@ -203,6 +205,7 @@ class Lattice:
         self.params = params
         self.boxes = list(boxes)
         self.C = params.ncomp
+        self.Q = 9 if int(getattr(params, "lattice", 0)) == 1 else 19
         if dtype not in STORAGE:
             raise ValueError(f"dtype must be one of {sorted(STORAGE)}")
         storage = STORAGE[dtype]
@@ -254,7 +257,7 @@ class Lattice:
         u = _c(box.u0.reshape(3, -1))
         phi = _c(box.phi0.reshape(-1))
         ubc = _c(box.u_bc.reshape(3, -1))
-        xi = _c(box.xi.reshape(self.C, Q, -1)) if box.xi is not None else None
+        xi = _c(box.xi.reshape(self.C, self.Q, -1)) if box.xi is not None else None
         self._keep = (t, rho, u, phi, ubc, xi)
         self._check(self.L.elbm_set_box(self.h, i, t.ctypes.data, rho.ctypes.data, u.ctypes.data,
                                         phi.ctypes.data, ubc.ctypes.data,
@@ -295,7 +298,7 @@ class Lattice:
         return al, it
 
     def get_populations(self, i: int = 0):
-        f = np.zeros((self.C, Q) + self._shape(i))
+        f = np.zeros((self.C, self.Q) + self._shape(i))
         self._check(self.L.elbm_get_populations(self.h, i, f.ctypes.data))
         return f
 

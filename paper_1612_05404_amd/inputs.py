@@ -53,6 +53,9 @@ def uniform(seed: int, n: int, lo: float, hi: float, offset: int = 0) -> np.ndar
 # --------------------------------------------------------------------------
 @dataclass
 class Params:
+    # lattice: 0 = D3Q19; 1 = D2Q9 (the paper's 2-D lattice; boxes with nz = 1,
+    # bounded in z)
+    lattice: int = 0
     ncomp: int = 2
     # Shan-Chen couplings G[s][t] and the fluid-wall couplings Gw[s][t]
     # (None: Gw = G, a neutral wall)
@@ -147,14 +150,14 @@ def drop_profile(nx, ny, nz, centre, radius, width, rho_in, rho_out, periodic) -
     return rho_out + (rho_in - rho_out) * 0.5 * (1.0 - np.tanh(2.0 * (d - radius) / width))
 
 
-def jitter_draws(seed: int, ncomp: int, n: int) -> np.ndarray:
-    """Jitter draws xi in [-1, 1): index (s * 19 + p) * n + node."""
-    return uniform(seed, ncomp * 19 * n, -1.0, 1.0).reshape(ncomp, 19, n)
+def jitter_draws(seed: int, ncomp: int, n: int, q: int = 19) -> np.ndarray:
+    """Jitter draws xi in [-1, 1): index (s * q + p) * n + node, q directions."""
+    return uniform(seed, ncomp * q * n, -1.0, 1.0).reshape(ncomp, q, n)
 
 
 def droplet_box(edge_x, edge_y, edge_z, radius, *, seed, periodic=(1, 1, 1), walls_z=False,
                 phi_bottom=0.0, phi_top=0.0, rho_in=1.0, rho_out=0.01, width=2.0,
-                jitter=1e-4, ncomp=2) -> Box:
+                jitter=1e-4, ncomp=2, q=19) -> Box:
     nx, ny, nz = edge_x, edge_y, edge_z
     n = nx * ny * nz
     t = np.zeros((nz, ny, nx), dtype=np.uint8)
@@ -175,7 +178,7 @@ def droplet_box(edge_x, edge_y, edge_z, radius, *, seed, periodic=(1, 1, 1), wal
         rho0 = rA[None]
     solid = (t & 3) == SOLID
     rho0[:, solid] = 0.0
-    xi = jitter_draws(seed, ncomp, n).reshape(ncomp, 19, nz, ny, nx)
+    xi = jitter_draws(seed, ncomp, n, q).reshape(ncomp, q, nz, ny, nx)
     return Box(nx, ny, nz, per, t, rho0, np.zeros((3, nz, ny, nx)), phi0,
                np.zeros((3, nz, ny, nx)), xi, jitter,
                info=dict(radius=radius, centre=centre))
@@ -280,4 +283,23 @@ def ensemble(seed: int = 1238, nboxes: int = 256, edges=(24, 32, 48, 64), steps:
     return Workload("ensemble", p, boxes, "f32", steps, info=dict(seed=seed))
 
 
-WORKLOADS = {"drop32": drop32, "efield_drop": efield_drop, "jet": jet, "ensemble": ensemble}
+def paper_drop_2d(n: int = 320, radius: float = 40.0, Q: float = 2.13, surface_ratio: float = 10.0,
+                  E_ext: float = 0.0, steps: int = 1000, width: float = 2.0, seed: int = 1240) -> Workload:
+    """The paper's charged drop (Sec. III.A) on its own lattice: a periodic
+    n x n D2Q9 mesh, one Shan-Chen fluid with G = -5 (psi = 1 - exp(-rho)), a
+    circular drop of density 2.0 and radius 40 in vapour of density 0.16, total
+    charge Q = Q_s + Q_b = 2.13 with Q_s / Q_b = 10 (Eq. surface-q2, K_d = 1),
+    a uniform neutralising charge, F_el = q E (the force the section uses),
+    Newtonian with nu = 1/6; E_ext along x for the drop in a field."""
+    box = droplet_box(n, n, 1, radius, seed=seed, periodic=(1, 1, 0), rho_in=2.0, rho_out=0.16, width=width,
+                      jitter=0.0, ncomp=1, q=9)
+    Q_b = Q / (1.0 + surface_ratio)
+    p = Params(lattice=1, ncomp=1, G=[[-5.0, 0.0], [0.0, 0.0]], carreau=0, nu0=1.0 / 6.0, Q_b=Q_b,
+               Q_s=Q - Q_b, K_d=1.0, curvature=1, electrostriction=0, rho_th=1.0, w_theta=0.05,
+               E_ext=[E_ext, 0.0, 0.0], sor_omega=sor_omega_opt(n, n, 1, True), sor_sweeps=400, sor_tol=1e-5,
+               sor_check_every=4, rho_in=[2.0, 0.0], rho_out=[0.16, 0.0])
+    return Workload("paper_drop_2d", p, [box], "f64", steps, info=dict(seed=seed, radius=radius, Q=Q))
+
+
+WORKLOADS = {"drop32": drop32, "efield_drop": efield_drop, "jet": jet, "ensemble": ensemble,
+             "paper_drop_2d": paper_drop_2d}

@@ -59,7 +59,11 @@ def _alpha_decimal(f, fe, w, lo, hi, iters=200):
     getcontext().prec = 60
     F = [Decimal(float(x)) for x in f]
     E = [Decimal(float(x)) for x in fe]
-    W = [Decimal(1) / Decimal(3)] + [Decimal(1) / Decimal(18)] * 6 + [Decimal(1) / Decimal(36)] * 12
+    # the lattice weights as exact decimals (given as Decimals, else D3Q19)
+    if isinstance(w, (list, tuple)) and isinstance(w[0], Decimal):
+        W = list(w)
+    else:
+        W = [Decimal(1) / Decimal(3)] + [Decimal(1) / Decimal(18)] * 6 + [Decimal(1) / Decimal(36)] * 12
     H0 = _H_dec(F, W)
 
     def g(a):
