@@ -299,6 +299,16 @@ elbm_status elbm_mlp_forward(elbm_ctx *ctx, const void *dX, void *dY, int64_t M)
  * (either may be NULL). */
 elbm_status elbm_mlp_grad(elbm_ctx *ctx, const void *dX, const void *dT, int64_t M, float *grad,
                           float *loss);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): the gradient of
+ * elbm_mlp_grad, enqueued on the bound stream without synchronising and
+ * written to device memory dGrad, float [1762] (the 1761 gradient entries in
+ * parameter order, then the loss).  Bitwise equal to elbm_mlp_grad's result.
+ * It allocates nothing: its scratch (64 block partials of 2146 floats, 549 KB,
+ * whatever M is) is a fixed device array of the library, one per GPU, kept
+ * until the process ends and fully rewritten by every call; calls that
+ * overlap on one GPU race for it.  EINVAL for NULL pointers or M <= 0. */
+elbm_status elbm_mlp_grad_noalloc(elbm_ctx *ctx, const void *dX, const void *dT, int64_t M, void *dGrad);
 /* steps (<= 4096) Adam steps (beta 0.9, 0.999, eps 1e-8, learning rate lr) on
  * consecutive batches of `batch` samples of device X [M][20], T [M], wrapping at
  * M (the caller shuffles); losses [steps] (host, may be NULL) receives each

@@ -22,6 +22,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -48,6 +49,7 @@ struct elbm_ctx {
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
+  int device = 0;  // the device current at bind (the arena's and the stream's)
   char *base = nullptr;
   hipStream_t stream = nullptr;
   // second stream for the alpha solve beside the field chain, and its fork/join events
@@ -486,6 +488,40 @@ size_t cur_pop_off(const elbm_ctx *c) { return c->parity ? c->o_fb : c->o_fa; }
     ELBM_DISPATCH_STORAGE(c, __VA_ARGS__)                       \
   }
 
+// ---- device scratch of the allocation-free entry point (elbm_mlp_grad_noalloc)
+// The gradient kernel's block partials live in a file-scope device array
+// instead of the arena: each GPU the library runs on holds one copy, at its
+// own address, until the process ends.  Host code never passes the array's
+// name to a kernel (in host code it is a stand-in, not a device address): the
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept in g_scratch_ptr.  Every call rewrites all of it
+// (each of the MLP_GGRID blocks stores all its MLP_GRAD_SLOTS partials), so
+// nothing needs clearing; calls that overlap on one GPU race for it.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = (size_t)MLP_GGRID * MLP_GRAD_SLOTS;  // 549 KB
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+elbm_status scratch_address(elbm_ctx *c, float **out) {
+  const int dev = c->device;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(c, ELBM_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(c, hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(c, ELBM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (float *)g_scratch_ptr[dev];
+  return ELBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -621,6 +657,7 @@ elbm_status elbm_bind(elbm_ctx *c, void *arena, size_t bytes, void *stream) {
   if (!arena || ((uintptr_t)arena & 255)) return fail(c, ELBM_EINVAL, "arena must be non-null and 256-byte aligned");
   if (bytes < c->total) return fail(c, ELBM_ENOMEM, "arena smaller than elbm_required_bytes");
   c->drop_graphs();
+  HIPCHK(c, hipGetDevice(&c->device));
   c->base = (char *)arena;
   c->stream = (hipStream_t)stream;
   if (!c->aux) {  // default priority, like the caller's stream
@@ -1006,6 +1043,24 @@ elbm_status elbm_mlp_grad(elbm_ctx *c, const void *dX, const void *dT, int64_t M
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (grad) HIPCHK(c, hipMemcpy(grad, g, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
   if (loss) HIPCHK(c, hipMemcpy(loss, g + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost));
+  return ELBM_OK;
+}
+
+elbm_status elbm_mlp_grad_noalloc(elbm_ctx *c, const void *dX, const void *dT, int64_t M, void *dGrad) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) return fail(c, ELBM_ESTATE, "context is not bound to an arena");
+  if (!dX || !dT || !dGrad || M <= 0) return fail(c, ELBM_EINVAL, "mlp_grad_noalloc: bad arguments");
+  // the scratch holds MLP_GGRID block partials whatever M is: no size of the
+  // call can exceed it
+  static_assert(NOALLOC_SCRATCH_FLOATS >= (size_t)MLP_GGRID * MLP_GRAD_SLOTS, "scratch too small for the grid");
+  float *part = nullptr;
+  elbm_status st = scratch_address(c, &part);
+  if (st) return st;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(MLP_GGRID), dim3(MLP_GBLK), 0, c->stream, make_mlp(c), (const float *)dX,
+                     (const float *)dT, (int64_t)0, M, 1.0f / (float)M, part);
+  hipLaunchKernelGGL(k_mlp_sum, dim3(1), dim3(BLK), 0, c->stream, (const float *)part, MLP_GGRID, (float *)dGrad,
+                     (float *)nullptr);
+  HIPCHK(c, hipGetLastError());
   return ELBM_OK;
 }
 

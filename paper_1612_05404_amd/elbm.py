@@ -79,7 +79,7 @@ SYMBOLS = [
     "elbm_sync", "elbm_read_moments", "elbm_read_potential", "elbm_read_charge", "elbm_read_alpha",
     "elbm_get_populations", "elbm_set_populations", "elbm_set_potential", "elbm_diagnostics",
     "elbm_set_graphs", "elbm_set_timing", "elbm_timing", "elbm_mlp_set_weights", "elbm_mlp_get_weights",
-    "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_train", "elbm_alpha_samples", "elbm_set_launch",
+    "elbm_mlp_forward", "elbm_mlp_grad", "elbm_mlp_grad_noalloc", "elbm_mlp_train", "elbm_alpha_samples", "elbm_set_launch",
     "elbm_get_launch", "elbm_autotune", "elbm_last_error", "elbm_destroy",
 ]
 TUNE_CANDIDATES = 11
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     L.elbm_mlp_get_weights.argtypes = [vp, vp, i64]
     L.elbm_mlp_forward.argtypes = [vp, vp, vp, i64]
     L.elbm_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.elbm_mlp_grad_noalloc.argtypes = [vp, vp, vp, i64, vp]
     L.elbm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ct.c_float, vp]
     L.elbm_alpha_samples.argtypes = [vp, i32, vp, vp, vp, vp]
     L.elbm_set_launch.argtypes = [vp, ct.POINTER(elbm_launch)]
@@ -366,6 +367,17 @@ class Lattice:
         self._check(self.L.elbm_mlp_grad(self.h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()), X.shape[0],
                                          g.ctypes.data, ct.byref(loss)))
         return g, loss.value
+
+    def mlp_grad_noalloc(self, X, T, G):
+        """The gradient and loss into the device tensor G (float32 [1762]),
+        enqueued on the library's stream with no allocation and no
+        synchronisation (the library's allocation-free entry point)."""
+        import torch
+        X, T = X.contiguous(), T.contiguous()
+        assert G.dtype == torch.float32 and G.numel() == self.MLP_NPARAM + 1 and G.is_contiguous()
+        self.stream.wait_stream(torch.cuda.current_stream(X.device))
+        self._check(self.L.elbm_mlp_grad_noalloc(self.h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()),
+                                                 X.shape[0], ct.c_void_p(G.data_ptr())))
 
     def mlp_train(self, X, T, batch: int, steps: int, lr: float):
         """Adam steps over consecutive batches of (X, T); returns the batch losses."""
