@@ -47,6 +47,7 @@ class OraParams(ct.Structure):
         ("sor_omega", ct.c_double), ("newton_rtol", ct.c_double),
         ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
         ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("lattice", ct.c_int32),
+        ("inlet_mode", ct.c_int32), ("pad2_", ct.c_int32),
     ]
 
 
@@ -82,6 +83,8 @@ def lib():
         L.ora_shear_rate.restype = ct.c_double
         L.ora_shear_rate.argtypes = [ct.c_double] * 7
         L.ora_lattice.argtypes = [ct.c_void_p, ct.c_void_p]
+        L.ora_inlet_ubar.restype = ct.c_double
+        L.ora_inlet_ubar.argtypes = [ct.c_void_p]
         L.ora_lattice_q.restype = ct.c_int
         L.ora_lattice_q.argtypes = [ct.c_int, ct.c_void_p, ct.c_void_p]
         L.ora_feq_lat.argtypes = [ct.c_int, ct.c_double, dp, dp]
@@ -178,6 +181,7 @@ def make_params(p, box, nthreads: int = 0) -> OraParams:
     P.sor_tol = float(getattr(p, "sor_tol", 0.0))
     P.sor_check_every = int(getattr(p, "sor_check_every", 0))
     P.lattice = int(getattr(p, "lattice", 0))
+    P.inlet_mode = int(getattr(p, "inlet_mode", 0))
     for s in range(2):
         P.rho_in[s] = p.rho_in[s]
         P.rho_out[s] = p.rho_out[s]
@@ -244,6 +248,11 @@ class Oracle:
     def set_phi(self, phi: np.ndarray):
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         lib().ora_set_phi(self.h, phi.ctypes.data)
+
+    def inlet_ubar(self) -> float:
+        """Mean velocity inside the nozzle measured in the last step (the
+        adaptive inlet, Sec. III.B); 0 without it."""
+        return float(lib().ora_inlet_ubar(self.h))
 
     def poisson_stats(self):
         """Residual, its scale max|rhs|, sweeps done of the last step's Poisson

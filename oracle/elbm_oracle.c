@@ -83,7 +83,7 @@ static const ora_lat *lattice_of(int id) { return id == 1 ? &LAT_D2Q9 : &LAT_D3Q
 
 static int opposite(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
 
-enum { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3, T_DIRICHLET = 4 };
+enum { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3, T_DIRICHLET = 4, T_NOZZLE = 8 };
 
 typedef struct {
     int32_t nx, ny, nz, ncomp;
@@ -103,6 +103,12 @@ typedef struct {
     double sor_tol;
     int32_t sor_check_every;
     int32_t lattice;  /* 0: D3Q19, 1: D2Q9 (nz = 1, bounded in z) */
+    /* inlet: 0 the neighbour-density velocity inlet (u_bc as given); 1 + a:
+     * the paper's jet inlet, density rho_in and velocity ubar * u_bc, ubar the
+     * mean velocity along axis a inside the nozzle (fluid nodes marked
+     * T_NOZZLE), measured every step */
+    int32_t inlet_mode;
+    int32_t pad2_;
 } ora_params;
 
 typedef struct {
@@ -136,6 +142,7 @@ typedef struct {
     double *uph;    /* [3][N] half-step barycentric velocity */
     double *u_bc;   /* [3][N] inlet velocity */
     double qbar;
+    double ubar;    /* mean velocity inside the nozzle of this step's moments */
     double Sb, Ss;
     int64_t nfallback;
     int64_t nerr_nonfinite, nerr_negative;
@@ -444,7 +451,8 @@ static void boundary_populations(ora_state *s, int64_t n, int sigma, double *out
     double u[3] = {0, 0, 0};
     double r;
     if (kind(s, n) == T_INLET) {
-        u[0] = s->u_bc[n]; u[1] = s->u_bc[s->N + n]; u[2] = s->u_bc[2 * s->N + n];
+        const double sc = s->P.inlet_mode > 0 ? 0.0 : 1.0;  /* the adaptive inlet starts from rest */
+        u[0] = sc * s->u_bc[n]; u[1] = sc * s->u_bc[s->N + n]; u[2] = sc * s->u_bc[2 * s->N + n];
         r = s->P.rho_in[sigma];
     } else {
         r = s->P.rho_out[sigma];
@@ -523,6 +531,21 @@ static void stream_and_moments(ora_state *s) {
                     s->psi[(int64_t)sg * N + n] = (k == T_SOLID) ? 0.0 : -expm1(-r);
                 }
             }
+    /* the jet inlet's measurement (Sec. III.B): mean velocity of the fluid in
+     * the nozzle, total momentum along the inlet axis over total mass */
+    s->ubar = 0.0;
+    if (s->P.inlet_mode > 0) {
+        const int a = s->P.inlet_mode - 1;
+        double jsum = 0.0, msum = 0.0;
+        for (int64_t n = 0; n < N; ++n) {
+            if (kind(s, n) != T_FLUID || !(s->type[n] & T_NOZZLE)) continue;
+            for (int sg = 0; sg < C; ++sg) {
+                jsum += s->jm[((int64_t)sg * 3 + a) * N + n];
+                msum += s->rho[(int64_t)sg * N + n];
+            }
+        }
+        s->ubar = msum > 0.0 ? jsum / msum : 0.0;
+    }
 }
 
 /* Isotropic 19-point gradient (1/c_s^2) sum_p w_p c_p X(r + c_p).
@@ -834,14 +857,23 @@ static void forces(ora_state *s) {
 }
 
 /* Velocity inlet (the jet set-up of Sec. III.B: Poiseuille velocity at the
- * inlet nodes, density that of the liquid): after each step's moments an
- * inlet node holds f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted
- * mean density of its fluid neighbours, sum_p w_p rho(r + c_p) / sum_p w_p
- * (rho_in when it has none). */
+ * inlet nodes, density that of the liquid).  After each step's moments an
+ * inlet node holds, per component,
+ *   inlet_mode 0: f_eq(rho_nb, u_bc), rho_nb the w-weighted mean density of
+ *     its fluid neighbours, sum_p w_p rho(r + c_p) / sum_p w_p (rho_in when it
+ *     has none);
+ *   inlet_mode 1 + a: f_eq(rho_in, ubar u_bc), the profile u_bc rescaled by
+ *     the mean velocity measured inside the nozzle in the same step (the
+ *     paper's inlet). */
 static void inlet_populations(const ora_state *s, int x, int y, int z, int sg, double *out) {
     LAT_LOCALS(s);
     const int64_t N = s->N;
     const int64_t n = node_index(s, x, y, z);
+    if (s->P.inlet_mode > 0) {
+        double u[3] = {s->ubar * s->u_bc[n], s->ubar * s->u_bc[N + n], s->ubar * s->u_bc[2 * N + n]};
+        feq_lat(s->lat, s->P.rho_in[sg], u, out);
+        return;
+    }
     double sw = 0.0, sr = 0.0;
     for (int p = 1; p < Q; ++p) {
         int64_t m = neighbour(s, x, y, z, CV[p][0], CV[p][1], CV[p][2]);
@@ -1014,6 +1046,9 @@ void ora_poisson_stats(const ora_state *s, double out_d[2], int64_t out_i[2]) {
     out_d[0] = s->sor_res; out_d[1] = s->sor_scale;
     out_i[0] = s->sor_done; out_i[1] = s->sor_noconv;
 }
+
+/* Mean velocity inside the nozzle measured in the last step (inlet_mode > 0). */
+double ora_inlet_ubar(const ora_state *s) { return s->ubar; }
 
 /* Lattice tables (for the tests): D3Q19. */
 void ora_lattice(int32_t c[19 * 3], double w[19]) {

@@ -23,6 +23,7 @@ import numpy as np
 
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 DIRICHLET = 4
+NOZZLE = 8      # fluid node inside the nozzle: enters the adaptive inlet's mean velocity
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -92,6 +93,10 @@ class Params:
     # boundary densities (per component) of inlet and outlet nodes
     rho_in: List[float] = field(default_factory=lambda: [1.0, 0.01])
     rho_out: List[float] = field(default_factory=lambda: [0.01, 1.0])
+    # inlet: 0 velocity u_bc at the neighbours' density; 1 + a: density rho_in
+    # and velocity ubar * u_bc, ubar the mean velocity along axis a of the
+    # fluid in the nozzle (NOZZLE nodes), measured every step
+    inlet_mode: int = 0
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)
@@ -301,5 +306,66 @@ def paper_drop_2d(n: int = 320, radius: float = 40.0, Q: float = 2.13, surface_r
     return Workload("paper_drop_2d", p, [box], "f64", steps, info=dict(seed=seed, radius=radius, Q=Q))
 
 
+PAPER_JET_CASES = {
+    # Sec. III.B: case a Newtonian; b and c Carreau with nu_inf = 0.001,
+    # lambda = 1000 and flow index 0.75 / 0.5
+    "a": dict(carreau=0, n_flow=1.0),
+    "b": dict(carreau=1, n_flow=0.75),
+    "c": dict(carreau=1, n_flow=0.5),
+}
+
+
+def paper_jet_2d(case: str = "b", n: int = 320, diameter: int = 40, nozzle_len: int = 40, wall: int = 4,
+                 E0: float = 0.1, steps: int = 25000, width: float = 2.0, seed: int = 1241) -> Workload:
+    """The paper's electrospinning set-up (Sec. III.B) on its own lattice: an
+    n x n D2Q9 mesh, one Shan-Chen fluid (G = G_w = -5), bounce-back walls on
+    the bottom and top rows, a nozzle of inner diameter 40 on the left (a tube
+    of `wall`-node walls reaching `nozzle_len` nodes into the box from a solid
+    left column that holds the inlet nodes), outlet nodes on the right column
+    in contact with a gas reservoir (density 0.16), the generator charge model
+    (Eq. surface-q3, xi_b = 1e-4, xi_s = 6e-2, K_d = 1) and Dirichlet
+    potentials on every edge, phi = -E0 (x + 1) (phi = 0 one node left of the
+    box, a uniform field E0 = 0.1 along x).  The inlet holds the liquid
+    density 2.0 and a Poiseuille profile 1.5 (1 - (y - y_c)^2 / a0^2) (unit
+    mean) scaled every step by the mean velocity inside the nozzle.  Liquid
+    (2.0) fills the nozzle with a drop of radius a0 = diameter/2 just outside
+    it; gas (0.16) elsewhere.  `case`: "a" Newtonian nu = 1/6, "b" / "c"
+    Carreau (nu0 = 1/6, nu_inf = 0.001, lambda = 1000, n = 0.75 / 0.5)."""
+    a0 = diameter / 2.0
+    yc = (n - 1) / 2.0
+    xx = np.arange(n, dtype=np.float64)[None, :]
+    yy = np.arange(n, dtype=np.float64)[:, None]
+    dy = np.abs(yy - yc) + 0.0 * xx
+    chan = dy < a0
+    tube = (dy > a0) & (dy < a0 + wall) & (xx < nozzle_len)
+    t = np.full((n, n), FLUID, dtype=np.uint8)
+    t[tube] = SOLID
+    t[:, -1] = OUTLET
+    t[:, 0] = np.where(chan[:, 0], INLET, SOLID)
+    t[0, :] = SOLID
+    t[-1, :] = SOLID
+    edge = np.zeros((n, n), dtype=bool)
+    edge[:, 0] = edge[:, -1] = edge[0, :] = edge[-1, :] = True
+    t[edge] |= DIRICHLET
+    t[chan & (xx >= 1) & (xx < nozzle_len) & ((t & 3) == FLUID)] |= NOZZLE
+    phi0 = -E0 * (xx + 1.0) + 0.0 * yy
+    u_bc = np.zeros((3, 1, n, n))
+    u_bc[0, 0] = np.where(t == (INLET | DIRICHLET), 1.5 * (1.0 - ((yy - yc) / a0) ** 2), 0.0)
+    drop = drop_profile(n, n, 1, (float(nozzle_len), yc, 0.0), a0, width, 2.0, 0.16, (0, 0, 0))[0]
+    rho = np.where(chan & (xx < nozzle_len), 2.0, drop)
+    rho = np.where((t & 3) == SOLID, 0.0, rho)
+    rho = np.where((t & 3) == INLET, 2.0, rho)
+    rho = np.where((t & 3) == OUTLET, 0.16, rho)
+    xi = jitter_draws(seed, 1, n * n, q=9).reshape(1, 9, 1, n, n)
+    box = Box(n, n, 1, [0, 0, 0], t[None].copy(), rho[None, None].copy(), np.zeros((3, 1, n, n)), phi0[None].copy(),
+              u_bc, xi, 0.0, info=dict(case=case, a0=a0, nozzle_len=nozzle_len, wall=wall, E0=E0))
+    p = Params(lattice=1, ncomp=1, G=[[-5.0, 0.0], [0.0, 0.0]], Gw=[[-5.0, 0.0], [0.0, 0.0]], nu0=1.0 / 6.0,
+               nu_inf=0.001, lam=1000.0, charge_model=1, xi_b=1e-4, xi_s=6e-2, K_d=1.0, curvature=1,
+               electrostriction=0, rho_th=1.0, w_theta=0.05, E_ext=[0.0, 0.0, 0.0],
+               sor_omega=sor_omega_opt(n, n, 1, False), sor_sweeps=400, sor_tol=1e-5, sor_check_every=4,
+               rho_in=[2.0, 0.0], rho_out=[0.16, 0.0], inlet_mode=1, **PAPER_JET_CASES[case])
+    return Workload("paper_jet_2d", p, [box], "f64", steps, info=dict(seed=seed, case=case))
+
+
 WORKLOADS = {"drop32": drop32, "efield_drop": efield_drop, "jet": jet, "ensemble": ensemble,
-             "paper_drop_2d": paper_drop_2d}
+             "paper_drop_2d": paper_drop_2d, "paper_jet_2d": paper_jet_2d}
