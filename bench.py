@@ -330,6 +330,7 @@ def main():
             "same_fallback_nodes_as_plain": v["same_fallbacks"],
             "window_fallback_frac": round(v["nfb"] / max(v["ncol"], 1), 7),
             "window_negative_pop_frac": round(v["neg"] / max(19 * v["ncol"], 1), 8),
+            "window_end_sor_residual_rel": round(v["d1"]["sor_residual"] / max(v["d1"]["sor_scale"], 1e-300), 6),
             "launch": v["launch"],
         }
     out = {

@@ -42,11 +42,13 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 5u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
+#define ELBM_ABI_VERSION 6u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
                                  3: sweep_priority in elbm_launch;
                                  4: Poisson stop rule and residual, strict error flags, Halley
                                     iteration, electric force and solver fields in elbm_diag;
-                                 5: the lattice (D3Q19 or the paper's D2Q9) in elbm_params */
+                                 5: the lattice (D3Q19 or the paper's D2Q9) in elbm_params;
+                                 6: the adaptive jet inlet (inlet_mode, NOZZLE nodes, the
+                                    measured mean velocity in elbm_diag) */
 
 typedef struct elbm_ctx elbm_ctx;
 
@@ -75,6 +77,24 @@ enum { ELBM_STRICT_NEGPOP = 1, ELBM_STRICT_ALPHA = 2 };
  * nz = 1 and bounded in z (the Poisson problem then has no z faces);
  * populations are [C][9][N]. */
 enum { ELBM_LATTICE_D3Q19 = 0, ELBM_LATTICE_D2Q9 = 1 };
+
+/* Node type byte (elbm_set_box): bits 0-1 the kind, FLUID 0, SOLID 1 (halfway
+ * bounce-back), INLET 2, OUTLET 3; bit 2 DIRICHLET (the potential is held at
+ * its initial value); bit 3 NOZZLE, on fluid nodes only: the node enters the
+ * mean velocity that the adaptive inlet measures. */
+enum { ELBM_NODE_FLUID = 0, ELBM_NODE_SOLID = 1, ELBM_NODE_INLET = 2, ELBM_NODE_OUTLET = 3,
+       ELBM_NODE_DIRICHLET = 4, ELBM_NODE_NOZZLE = 8 };
+
+/* Inlet nodes (the jet set-up of Sec. III.B).  NEIGHBOUR: each step an inlet
+ * node is reset to f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted
+ * mean density of its fluid neighbours (rho_in when it has none).
+ * ADAPTIVE_X/Y/Z, the paper's inlet: f_eq(rho_in, ubar u_bc), u_bc the
+ * velocity profile (its shape; a unit mean gives the measured flow rate) and
+ * ubar the mean velocity of the fluid inside the nozzle along that axis,
+ * sum_nozzle sum_s j_s / sum_nozzle sum_s rho_s over the NOZZLE nodes, from
+ * the same step's streamed moments; inlet nodes start from rest. */
+enum { ELBM_INLET_NEIGHBOUR = 0, ELBM_INLET_ADAPTIVE_X = 1, ELBM_INLET_ADAPTIVE_Y = 2,
+       ELBM_INLET_ADAPTIVE_Z = 3 };
 
 /* Storage: F64 = FP64 populations and fields; F32 = FP32 populations with
  * FP64 auxiliary fields (densities, psi, charge, potential, |E|^2);
@@ -115,8 +135,9 @@ typedef struct {
     double rho_th, w_theta;   /* smoothed Heaviside: 0.5(1+tanh((rho-rho_th)/w))    */
     double xi_b, xi_s;        /* generator-connected charge constants (Eq. surface-q3) */
     double newton_rtol;       /* alpha converged when |dH| <= rtol * scale          */
-    double rho_in[2];         /* inlet densities at start, and for an inlet node
-                                 without fluid neighbours                           */
+    double rho_in[2];         /* inlet densities: at start, for a neighbour inlet
+                                 node without fluid neighbours, and always with an
+                                 adaptive inlet                                     */
     double rho_out[2];        /* component densities held at outlet nodes           */
     double sor_tol;           /* > 0: Poisson sweeps stop once the residual
                                  max|sum_f eps_f (phi_nb - phi) - rhs| is at most
@@ -127,7 +148,7 @@ typedef struct {
                                  many sweeps (0: after the last only)              */
     int32_t alpha_iter;       /* ELBM_ITER_*                                        */
     int32_t lattice;          /* ELBM_LATTICE_* (the learned starter: D3Q19 only)    */
-    int32_t pad2_;
+    int32_t inlet_mode;       /* ELBM_INLET_*                                       */
 } elbm_params;
 
 /* One lattice box.  Boxes of one context are independent (no exchange). */
@@ -162,6 +183,8 @@ typedef struct {
     int32_t sor_sweeps;       /* sweeps that solve ran                              */
     int32_t pad_;
     int64_t n_sor_noconv;     /* solves that ended above sor_tol, all steps        */
+    double inlet_ubar;        /* mean velocity inside the nozzle measured by the
+                                 adaptive inlet in the last step (0 without it)    */
 } elbm_diag;
 
 /* ABI version of the loaded library (ELBM_ABI_VERSION). */
@@ -189,12 +212,12 @@ elbm_status elbm_bind(elbm_ctx *ctx, void *dev_arena, size_t bytes, void *hip_st
  *  initial velocity; phi [N] initial potential (Dirichlet nodes keep it);
  *  u_bc [3][N] inlet velocity (read at inlet nodes only; may be NULL);
  *  xi [C][19][N] jitter draws (may be NULL = no jitter); jitter amplitude.
+ * node_type bytes are ELBM_NODE_* (NOZZLE only on fluid nodes; EINVAL otherwise).
  * Fluid nodes start at f = f_eq(rho, u) (1 + jitter * xi), inlet nodes at
- * f_eq(rho_in, u_bc), outlet nodes at f_eq(rho_out, 0), solid nodes at 0.
- * Every step resets an inlet node to f_eq(rho_nb, u_bc) per component, rho_nb
- * the w-weighted mean density of its fluid neighbours (a velocity inlet whose
- * density is that of the liquid next to it, as in the jet set-up of Sec. III.B);
- * outlet nodes keep theirs. */
+ * f_eq(rho_in, u_bc) (at rest with an adaptive inlet), outlet nodes at
+ * f_eq(rho_out, 0), solid nodes at 0.  Every step resets the inlet nodes as
+ * elbm_params.inlet_mode says (the jet set-up of Sec. III.B); outlet nodes
+ * keep theirs. */
 elbm_status elbm_set_box(elbm_ctx *ctx, int32_t box, const uint8_t *node_type, const double *rho,
                          const double *u, const double *phi, const double *u_bc, const double *xi,
                          double jitter);

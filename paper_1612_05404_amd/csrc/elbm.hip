@@ -45,7 +45,7 @@ struct elbm_ctx {
   size_t esz_pop = 8, esz_fld = 8;
   // arena offsets (bytes)
   size_t o_fa, o_fb, o_rho, o_psi, o_grad, o_bulk, o_surf, o_q, o_phi, o_rhs, o_e2, o_recu, o_ubc, o_ab, o_nbm, o_reca,
-      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_scal, o_cnt, o_err, total;
+      o_reci, o_type, o_stage, o_boxes, o_bb, o_part, o_rpart, o_fpart, o_npart, o_scal, o_cnt, o_err, total;
   // learned alpha starter: FP32 master + Adam moments, BF16 matrices, gradient, partials, losses
   size_t o_mp, o_mm, o_mv, o_mw1, o_mw2, o_mw2t, o_mgrad, o_mpart, o_mloss;
   int64_t adam_t = 0;
@@ -122,6 +122,7 @@ Model make_model(const elbm_params &P) {
   M.strict = P.strict;
   M.alpha_iter = P.alpha_iter;
   M.sor_check_every = P.sor_check_every;
+  M.inlet_mode = P.inlet_mode;
   M.sor_tol = P.sor_tol;
   for (int s = 0; s < 2; ++s)
     for (int t = 0; t < 2; ++t) {
@@ -171,6 +172,7 @@ Ptrs<T, F> make_ptrs(elbm_ctx *c) {
   a.partials = (double *)(b + c->o_part);
   a.res_part = (double *)(b + c->o_rpart);
   a.fel_part = (double *)(b + c->o_fpart);
+  a.noz_part = (double *)(b + c->o_npart);
   a.scal = (double *)(b + c->o_scal);
   a.cnt = (unsigned long long *)(b + c->o_cnt);
   a.err = (uint32_t *)(b + c->o_err);
@@ -255,7 +257,7 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   const bool fork = !c->timing;
   hipStream_t as = fork ? c->aux : c->stream;
   mark(c, ev, 0);
-  hipLaunchKernelGGL((k_density<Lat, T, F, C>), grid, blk, 0, c->stream, a);
+  hipLaunchKernelGGL((k_density<Lat, T, F, C>), grid, blk, 0, c->stream, a, c->P.inlet_mode - 1);
   mark(c, ev, 1);
   // the alpha kernel (the learned starter reads the 19 D3Q19 ratios)
   auto alpha_pass = [&]() {
@@ -276,7 +278,8 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   }
   hipLaunchKernelGGL((k_gradient<Lat, T, F>), grid, blk, 0, c->stream, a);
   hipLaunchKernelGGL((k_interface<Lat, T, F>), grid, blk, 0, c->stream, a, M);
-  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, a.scal, M, a.prio);
+  hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, (const double *)a.noz_part,
+                     a.scal, M, a.prio);
   hipLaunchKernelGGL((k_charge_rhs<T, F>), grid, blk, 0, c->stream, a);
   mark(c, ev, 2);
   // red-black sweeps; with a tolerance the FP64 residual is checked after
@@ -542,6 +545,8 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   if (P->lattice != ELBM_LATTICE_D3Q19 && P->lattice != ELBM_LATTICE_D2Q9) return ELBM_EINVAL;
   const bool two_d = P->lattice == ELBM_LATTICE_D2Q9;
   if (two_d && P->alpha_guess == ELBM_GUESS_MLP) return ELBM_EINVAL;  // the network reads 19 ratios
+  if (P->inlet_mode < ELBM_INLET_NEIGHBOUR || P->inlet_mode > ELBM_INLET_ADAPTIVE_Z) return ELBM_EINVAL;
+  if (two_d && P->inlet_mode == ELBM_INLET_ADAPTIVE_Z) return ELBM_EINVAL;  // one x-y plane
   if (P->charge_model != ELBM_CHARGE_CONSERVING && P->charge_model != ELBM_CHARGE_GENERATOR) return ELBM_EINVAL;
   if (!(P->w_theta > 0.0) || !(P->K_d > 0.0) || !(P->nu0 > 0.0) || !(P->newton_rtol > 0.0)) return ELBM_EINVAL;
   if (P->carreau && !(P->nu_inf > 0.0 && P->lam >= 0.0)) return ELBM_EINVAL;
@@ -625,6 +630,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->o_part = take(sizeof(double) * 4 * (size_t)c->nblocks);
   c->o_rpart = take(sizeof(double) * 2 * (size_t)c->nblocks);
   c->o_fpart = take(sizeof(double) * 3 * (size_t)c->nblocks);
+  c->o_npart = take(sizeof(double) * 2 * (size_t)c->nblocks);
   c->o_scal = take(sizeof(double) * NSCAL * nboxes);
   c->o_cnt = take(sizeof(unsigned long long) * NCNT * nboxes);
   c->o_err = take(sizeof(uint32_t) * 4);
@@ -700,7 +706,8 @@ elbm_status elbm_set_box(elbm_ctx *c, int32_t box, const uint8_t *type, const do
   int64_t nu = 0;
   bool dir = false;
   for (int i = 0; i < B.n; ++i) {
-    if (type[i] > 7) return fail(c, ELBM_EINVAL, "node type byte out of range");
+    if (type[i] > 15) return fail(c, ELBM_EINVAL, "node type byte out of range");
+    if ((type[i] & B_NOZZLE) && (type[i] & 3) != K_FLUID) return fail(c, ELBM_EINVAL, "NOZZLE bit on a non-fluid node");
     if (type[i] & B_DIRICHLET) dir = true; else ++nu;
   }
   B.has_dirichlet = dir ? 1 : 0;
@@ -957,6 +964,7 @@ elbm_status elbm_diagnostics(elbm_ctx *c, int32_t box, elbm_diag *out) {
   out->sor_residual = sc[4];
   out->sor_scale = sc[5];
   out->sor_sweeps = (int32_t)sc[6];
+  out->inlet_ubar = sc[8];
   unsigned long long cn[NCNT];
   HIPCHK(c, hipMemcpy(cn, c->base + c->o_cnt + sizeof(unsigned long long) * NCNT * box, sizeof(cn), hipMemcpyDeviceToHost));
   out->n_fallback = (int64_t)cn[0];

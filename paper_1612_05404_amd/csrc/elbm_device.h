@@ -13,7 +13,7 @@ namespace elbm {
 
 constexpr int NQ = 19;
 constexpr int BLK = 256;
-constexpr int K_FLUID = 0, K_SOLID = 1, K_INLET = 2, K_OUTLET = 3, B_DIRICHLET = 4;
+constexpr int K_FLUID = 0, K_SOLID = 1, K_INLET = 2, K_OUTLET = 3, B_DIRICHLET = 4, B_NOZZLE = 8;
 
 // D3Q19 velocity set (order documented in elbm.h).
 constexpr int kCx[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -33,14 +33,14 @@ __host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p 
 // x-y plane (nz = 1, bounded in z).  Opposite directions sit at adjacent
 // (odd, even) indices in both, so opp() serves both.
 struct D3Q19 {
-  static constexpr int Q = 19;
+  static constexpr int Q = 19, D = 3;
   static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
   static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
   static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
   __host__ __device__ static constexpr double w(int p) { return wgt(p); }
 };
 struct D2Q9 {
-  static constexpr int Q = 9;
+  static constexpr int Q = 9, D = 2;
   static constexpr int cx[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
   static constexpr int cy[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
   static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -65,6 +65,7 @@ struct BoxDev {
 struct Model {
   int32_t C, carreau, curvature, electrostriction, charge_model, newton_max, alpha_guess, strict;
   int32_t alpha_iter, sor_check_every;
+  int32_t inlet_mode;  // ELBM_INLET_*
   double G[2][2], Gw[2][2], nu0, nu_inf, lam, K_d, rho_th, w_theta, xi_b, xi_s, rtol;
   double rho_in[2], rho_out[2];
   double sor_tol;
@@ -73,8 +74,9 @@ struct Model {
 // scalars per box: [0] charge scale of the bulk part, [1] of the surface
 // part, [2] neutralising charge qbar, [3] mean potential, [4] Poisson
 // residual of the last check, [5] its scale max|rhs|, [6] sweeps done at
-// that check, [7] 1 once this step's solve has met its tolerance
-constexpr int NSCAL = 8;
+// that check, [7] 1 once this step's solve has met its tolerance, [8] mean
+// velocity inside the nozzle (adaptive inlet)
+constexpr int NSCAL = 9;
 // counters per box: fallbacks, Newton updates, negative f, non-finite f,
 // collisions, Poisson solves above their tolerance
 constexpr int NCNT = 8;
@@ -98,6 +100,7 @@ struct Ptrs {
   double *partials;     // [nblocks][4]
   double *res_part;     // [nblocks][2] Poisson residual and max|rhs| per block
   double *fel_part;     // [nblocks][3] electric force summed per block (recorded steps)
+  double *noz_part;     // [nblocks][2] momentum along the inlet axis and mass of NOZZLE nodes per block
   double *scal;         // [nboxes][NSCAL]
   unsigned long long *cnt;  // [nboxes][NCNT]
   uint32_t *err;
@@ -466,7 +469,7 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
                                                   double uz, int guess, double rtol) {
   const double uu = ux * ux + uy * uy + uz * uz;
   const double irho = rcp_nr(rho);
-  double xmax = 0.0, amax = INFINITY, L = 0.0;
+  double xmax = 0.0, xmin = 0.0, L = 0.0;
   double M[SERIES_DEG];  // M[k - 2] = M_k, k = 2 .. SERIES_DEG + 1
 #pragma unroll
   for (int k = 0; k < SERIES_DEG; ++k) M[k] = 0.0;
@@ -480,7 +483,7 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
     nonpos |= !(fp > 0.0);
     xs[p * XSTRIDE] = x;
     xmax = fmax(xmax, fabs(x));
-    if (x < 0.0) amax = fmin(amax, -rcp_nr(x));
+    xmin = fmin(xmin, x);
     L += d * log1p_fast((fp - wr) * (irho * (1.0 / Lat::w(p))));
     double t = fp * x * x;
 #pragma unroll
@@ -489,6 +492,8 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
       t *= x;
     }
   }
+  // top of the positivity interval, min over x_p < 0 of -1/x_p = -1/min x
+  const double amax = xmin < 0.0 ? -rcp_nr(xmin) : INFINITY;
   AlphaSetup st;
   st.M2 = M[0];
   st.L = L;

@@ -42,40 +42,57 @@ __global__ __launch_bounds__(BLK) void k_neighbour_mask(Ptrs<T, F> a, uint32_t *
 
 // Streaming (left side of Eq. lattice-b) by pulling + densities and the
 // Shan-Chen pseudo-potential psi = 1 - exp(-rho) (rho_0 = 1).  Sums run in
-// the field type F in the order p = 0..18.
+// the field type F in the order p = 0..18.  inlet_axis >= 0 (the adaptive
+// inlet of the jet set-up, Sec. III.B): NOZZLE fluid nodes also sum their
+// momentum along that axis, and every block stores its nodes' momentum and
+// mass sums (fixed order) for the per-box mean velocity.
 template <typename Lat, typename T, typename F, int C>
-__global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a) {
+__global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a, int inlet_axis) {
   Node nd;
   decode(a, nd);
-  if (!nd.live) return;
-  const int k = a.type[nd.g] & 3;
-  const uint32_t msk = a.nbm[nd.g];  // the source of p is the neighbour in direction opp(p)
-  int src[Lat::Q];
-  bool bb[Lat::Q];
-  src[0] = nd.n;
-  bb[0] = false;
+  double acc[2] = {0.0, 0.0};
+  if (nd.live) {
+    const uint8_t tt = a.type[nd.g];
+    const int k = tt & 3;
+    const bool noz = inlet_axis >= 0 && (tt & B_NOZZLE) && k == K_FLUID;
+    const uint32_t msk = a.nbm[nd.g];  // the source of p is the neighbour in direction opp(p)
+    int src[Lat::Q];
+    bool bb[Lat::Q];
+    src[0] = nd.n;
+    bb[0] = false;
 #pragma unroll
-  for (int p = 1; p < Lat::Q; ++p) {
-    src[p] = nbr(nd.B, nd.x, nd.y, nd.z, -Lat::cx[p], -Lat::cy[p], -Lat::cz[p]);
-    bb[p] = ((msk >> opp(p)) & 1u) || src[p] < 0;
-  }
+    for (int p = 1; p < Lat::Q; ++p) {
+      src[p] = nbr(nd.B, nd.x, nd.y, nd.z, -Lat::cx[p], -Lat::cy[p], -Lat::cz[p]);
+      bb[p] = ((msk >> opp(p)) & 1u) || src[p] < 0;
+    }
 #pragma unroll
-  for (int s = 0; s < C; ++s) {
-    F r = F(0);
-    if (k == K_INLET || k == K_OUTLET) {
+    for (int s = 0; s < C; ++s) {
+      F r = F(0);
+      double j = 0.0;
+      if (k == K_INLET || k == K_OUTLET) {
 #pragma unroll
-      for (int p = 0; p < Lat::Q; ++p) r += F(a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.g]);
-    } else if (k == K_FLUID) {
+        for (int p = 0; p < Lat::Q; ++p) r += F(a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.g]);
+      } else if (k == K_FLUID) {
 #pragma unroll
-      for (int p = 0; p < Lat::Q; ++p) {
-        const T v = bb[p] ? a.fa[(int64_t)(s * Lat::Q + opp(p)) * a.N + nd.g]
-                          : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + src[p]];
-        r += F(v);
+        for (int p = 0; p < Lat::Q; ++p) {
+          const T v = bb[p] ? a.fa[(int64_t)(s * Lat::Q + opp(p)) * a.N + nd.g]
+                            : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + src[p]];
+          r += F(v);
+          if (noz) {
+            const int ca = inlet_axis == 0 ? Lat::cx[p] : inlet_axis == 1 ? Lat::cy[p] : Lat::cz[p];
+            if (ca) j += double(ca) * double(v);
+          }
+        }
+      }
+      a.rho[(int64_t)s * a.N + nd.g] = r;
+      a.psi[nd.g * C + s] = (k == K_SOLID) ? F(0) : -expm1(-r);  // [N][C]: one load per neighbour in k_collide
+      if (noz) {
+        acc[0] += j;
+        acc[1] += double(r);
       }
     }
-    a.rho[(int64_t)s * a.N + nd.g] = r;
-    a.psi[nd.g * C + s] = (k == K_SOLID) ? F(0) : -expm1(-r);  // [N][C]: one load per neighbour in k_collide
   }
+  if (inlet_axis >= 0) block_sum_store<2>(acc, a.noz_part + (int64_t)nd.blk * 2);
 }
 
 // 19-point isotropic gradient G = (1/c_s^2) sum_p w_p c_p rho_A(r + c_p) (a
@@ -170,15 +187,20 @@ __global__ __launch_bounds__(BLK) void k_interface(Ptrs<T, F> a, Model M) {
 // partials; then the charge scales (conserving: Q/integral, generator: xi)
 // and the neutralising background qbar = sum_unknown q / N_unknown.
 __global__ __launch_bounds__(BLK) void k_charge_coef(const BoxDev *boxes, const double *partials,
-                                                     double *scal, Model M, int prio) {
+                                                     const double *noz_part, double *scal, Model M, int prio) {
   const BoxDev B = boxes[blockIdx.x];
   field_chain_priority(prio);  // after the uniform box load
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < B.nblocks; i += BLK)
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < B.nblocks; i += BLK) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] += partials[(int64_t)(B.first_block + i) * 4 + k];
-  __shared__ double tot[4];
-  block_sum_store<4>(acc, tot);
+    if (M.inlet_mode > 0) {
+      acc[4] += noz_part[(int64_t)(B.first_block + i) * 2];
+      acc[5] += noz_part[(int64_t)(B.first_block + i) * 2 + 1];
+    }
+  }
+  __shared__ double tot[6];
+  block_sum_store<6>(acc, tot);
   __syncthreads();
   if (threadIdx.x == 0) {
     double cb, cs;
@@ -194,6 +216,8 @@ __global__ __launch_bounds__(BLK) void k_charge_coef(const BoxDev *boxes, const 
     o[1] = cs;
     o[2] = B.n_unknown > 0 ? (cb * tot[2] + cs * tot[3]) / (double)B.n_unknown : 0.0;
     o[7] = 0.0;  // this step's Poisson solve has not met its tolerance yet
+    // mean velocity inside the nozzle: momentum over mass of the NOZZLE nodes
+    o[8] = (M.inlet_mode > 0 && tot[5] > 0.0) ? tot[4] / tot[5] : 0.0;
   }
 }
 
@@ -401,12 +425,26 @@ __device__ __forceinline__ void refill_x(const T *f, double *xs, double rho, dou
 }
 
 // Velocity inlet (the jet set-up of Sec. III.B: Poiseuille velocity at the inlet
-// nodes, density that of the liquid): each step an inlet node is reset to
-// f_eq(rho_nb, u_bc) per component, rho_nb the w-weighted mean density of its
-// fluid neighbours (rho_in when it has none).  Written to the output buffer,
-// which the next step pulls from.
+// nodes, density that of the liquid): each step an inlet node is reset, per
+// component, to f_eq(rho_nb, u_bc), rho_nb the w-weighted mean density of its
+// fluid neighbours (rho_in when it has none), or, with the adaptive inlet, to
+// f_eq(rho_in, ubar u_bc), ubar the mean velocity measured inside the nozzle
+// this step.  Written to the output buffer, which the next step pulls from.
 template <typename Lat, typename T, typename F, int C>
 __device__ __forceinline__ void inlet_store(const Ptrs<T, F> &a, const Model &M, const Node &nd) {
+  if (M.inlet_mode > 0) {
+    const double ub = a.scal[(int64_t)nd.bb * NSCAL + 8];
+    const double ux = ub * double(a.ubc[nd.g]), uy = ub * double(a.ubc[a.N + nd.g]),
+                 uz = ub * double(a.ubc[2 * a.N + nd.g]);
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+#pragma unroll 1
+      for (int p = 0; p < Lat::Q; ++p)
+        a.fb[(int64_t)(s * Lat::Q + p) * a.N + nd.g] = T(feq<Lat, double>(p, M.rho_in[s], ux, uy, uz, uu));
+    }
+    return;
+  }
   double sw = 0.0, sr[C];
 #pragma unroll
   for (int s = 0; s < C; ++s) sr[s] = 0.0;
@@ -545,7 +583,9 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
       double nu = M.nu0;
       if (M.carreau) {
         // Pi = sum_p (f_p - f_eq_p) c_p c_p: the equilibrium's second moment is
-        // rho (c_s^2 I + u u) exactly for this f_eq, so only f is summed
+        // rho (c_s^2 I + u u) exactly for this f_eq over the lattice's own axes
+        // (none along z on D2Q9, where every c_z and u_z vanish), so only f is
+        // summed
         double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
 #pragma unroll 1
         for (int p = 0; p < Lat::Q; ++p) {
@@ -559,7 +599,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         }
         P00 -= dr * (CS2 + ux * ux);
         P11 -= dr * (CS2 + uy * uy);
-        P22 -= dr * (CS2 + uz * uz);
+        if (Lat::D == 3) P22 -= dr * (CS2 + uz * uz);
         P01 -= dr * (ux * uy);
         P02 -= dr * (ux * uz);
         P12 -= dr * (uy * uz);
@@ -833,7 +873,9 @@ __global__ __launch_bounds__(BLK) void k_init_dir(Ptrs<T, F> a, Model M, int box
     v = feq<Lat, double>(p, rho0[s * ps + n], ux, uy, uz, ux * ux + uy * uy + uz * uz);
     if (xi) v = v * (1.0 + amp * xi[n]);
   } else if (k == K_INLET) {
-    const double ux = ubc ? ubc[n] : 0.0, uy = ubc ? ubc[ps + n] : 0.0, uz = ubc ? ubc[2 * ps + n] : 0.0;
+    // an adaptive inlet starts from rest (no mean velocity measured yet)
+    const bool rest = M.inlet_mode > 0 || !ubc;
+    const double ux = rest ? 0.0 : ubc[n], uy = rest ? 0.0 : ubc[ps + n], uz = rest ? 0.0 : ubc[2 * ps + n];
     v = feq<Lat, double>(p, M.rho_in[s], ux, uy, uz, ux * ux + uy * uy + uz * uz);
   } else if (k == K_OUTLET) {
     v = feq<Lat, double>(p, M.rho_out[s], 0.0, 0.0, 0.0, 0.0);

@@ -26,6 +26,8 @@ STORAGE = {"f64": STORAGE_F64, "f32": STORAGE_F32, "f32all": STORAGE_F32_ALL}
 GUESS = {"standard": 0, "mlp": 1, "series": 2}
 # the alpha iteration (same stopping rule): Newton, or Halley with g''
 ITER = {"newton": 0, "halley": 1}
+# inlet nodes: neighbour-density velocity inlet, or the adaptive jet inlet along x / y / z
+INLET_NEIGHBOUR, INLET_ADAPTIVE_X, INLET_ADAPTIVE_Y, INLET_ADAPTIVE_Z = 0, 1, 2, 3
 Q = 19
 
 
@@ -45,7 +47,7 @@ class elbm_params(ct.Structure):
         ("rho_th", ct.c_double), ("w_theta", ct.c_double), ("xi_b", ct.c_double), ("xi_s", ct.c_double),
         ("newton_rtol", ct.c_double), ("rho_in", ct.c_double * 2), ("rho_out", ct.c_double * 2),
         ("sor_tol", ct.c_double), ("sor_check_every", ct.c_int32), ("alpha_iter", ct.c_int32),
-        ("lattice", ct.c_int32), ("pad2_", ct.c_int32),
+        ("lattice", ct.c_int32), ("inlet_mode", ct.c_int32),
     ]
 
 
@@ -69,7 +71,7 @@ class elbm_diag(ct.Structure):
         ("mean_newton_iters", ct.c_double), ("n_fallback", ct.c_int64), ("n_negative", ct.c_int64),
         ("n_collisions", ct.c_int64), ("sum_Fel", ct.c_double * 3), ("sor_residual", ct.c_double),
         ("sor_scale", ct.c_double), ("sor_sweeps", ct.c_int32), ("pad_", ct.c_int32),
-        ("n_sor_noconv", ct.c_int64),
+        ("n_sor_noconv", ct.c_int64), ("inlet_ubar", ct.c_double),
     ]
 
 
@@ -87,7 +89,7 @@ TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
-ABI_VERSION = 5  # include/elbm.h ELBM_ABI_VERSION
+ABI_VERSION = 6  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -159,6 +161,7 @@ def make_params(p, storage: int, guess: int = 0, alpha_iter: int = 0, strict: in
     P.sor_tol = float(getattr(p, "sor_tol", 0.0))
     P.sor_check_every = int(getattr(p, "sor_check_every", 0))
     P.lattice = int(getattr(p, "lattice", 0))
+    P.inlet_mode = int(getattr(p, "inlet_mode", 0))
     gw = p.G if p.Gw is None else p.Gw
     for s in range(2):
         for t in range(2):
@@ -318,7 +321,7 @@ class Lattice:
                     alpha_max=d.alpha_max, alpha_mean=d.alpha_mean, mean_newton_iters=d.mean_newton_iters,
                     n_fallback=d.n_fallback, n_negative=d.n_negative, n_collisions=d.n_collisions,
                     sum_Fel=list(d.sum_Fel), sor_residual=d.sor_residual, sor_scale=d.sor_scale,
-                    sor_sweeps=d.sor_sweeps, n_sor_noconv=d.n_sor_noconv)
+                    sor_sweeps=d.sor_sweeps, n_sor_noconv=d.n_sor_noconv, inlet_ubar=d.inlet_ubar)
 
     def set_graphs(self, enable: bool = True):
         self._check(self.L.elbm_set_graphs(self.h, int(bool(enable))))

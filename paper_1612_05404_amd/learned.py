@@ -116,29 +116,44 @@ def main():
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--samples", type=int, default=10_000_000,
+                    help="samples to collect (served nodes of the periodic drop and the drop under a field)")
+    ap.add_argument("--run-steps", type=int, default=2000, help="steps of each sampled run")
+    ap.add_argument("--every", type=int, default=20, help="steps between two snapshots of a run")
     args = ap.parse_args()
     import torch
     from . import elbm, inputs
     t0 = time.time()
     log = lambda m: print(f"{m} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    # runs of the two configurations the network serves, one seed after the
+    # other (the jitter draws and the drop's charge differ), until the target
+    # count is reached; a quarter of the samples from the FP64 periodic drop
     Xs, Ts = [], []
-    for name, snaps, every, per in (("drop32", 20, 10, 0), ("efield_drop", 20, 40, 0)):
-        wl = inputs.WORKLOADS[name]()
-        lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess="standard")
-        X, T = collect(lat, snaps, every, per_snapshot=per, seed=args.seed)
-        log(f"[samples] {name}: {X.shape[0]} valid samples, target mean {T.mean().item():.4f} "
-            f"std {T.std().item():.4f}")
-        Xs.append(X)
-        Ts.append(T)
-        lat.close()
+    have = {"drop32": 0, "efield_drop": 0}
+    want = {"drop32": args.samples // 4, "efield_drop": args.samples - args.samples // 4}
+    for name, base in (("drop32", 1234), ("efield_drop", 1235)):
+        k = 0
+        while have[name] < want[name] and k < 64:
+            wl = inputs.WORKLOADS[name](seed=base + 1000 * k)
+            lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess="standard")
+            X, T = collect(lat, args.run_steps // args.every, args.every, seed=args.seed + k)
+            lat.close()
+            X, T = X[: want[name] - have[name]], T[: want[name] - have[name]]
+            have[name] += X.shape[0]
+            Xs.append(X)
+            Ts.append(T)
+            log(f"[samples] {name} seed {base + 1000 * k}: {X.shape[0]} samples (total {have[name]}), "
+                f"target mean {T.mean().item():.4f} std {T.std().item():.4f}")
+            k += 1
     X, T = torch.cat(Xs), torch.cat(Ts)
+    log(f"[samples] {X.shape[0]} samples in all")
     wl = inputs.WORKLOADS["drop32"]()
     lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess="mlp")
     lat.mlp_set_weights(init_weights(args.seed))
-    train(lat, X, T, args.steps, log=log)
+    ls = train(lat, X, T, args.steps, log=log)
     w = lat.mlp_get_weights()
     np.save(args.out, w.astype(np.float32), allow_pickle=False)
-    log(f"[train] wrote {args.out}")
+    log(f"[train] final loss (mean of the last 500 steps) {float(np.mean(ls[-500:])):.4e}; wrote {args.out}")
 
 
 if __name__ == "__main__":

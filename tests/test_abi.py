@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_abi_version(lib):
     from paper_1612_05404_amd import elbm
-    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 5
+    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 6
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -97,7 +97,8 @@ def test_create_and_layout_without_gpu(lib):
 
 @pytest.mark.parametrize("field,value", [("ncomp", 3), ("storage", 5), ("sor_sweeps", -1), ("newton_max", 0),
                                          ("charge_model", 7), ("alpha_guess", 9), ("strict", 4), ("strict", -1),
-                                         ("alpha_iter", 2), ("sor_tol", -1e-3), ("sor_check_every", -2)])
+                                         ("alpha_iter", 2), ("sor_tol", -1e-3), ("sor_check_every", -2),
+                                         ("inlet_mode", 4), ("inlet_mode", -1)])
 def test_create_rejects_bad_params(lib, field, value):
     P, p = _params()
     setattr(P, field, value)
@@ -117,3 +118,19 @@ def test_create_rejects_bad_boxes(lib):
     assert lib.elbm_create(ct.byref(P), B, 1, ct.byref(h)) == -1
     assert lib.elbm_create(ct.byref(P), B, 0, ct.byref(h)) == -1
     assert lib.elbm_create(None, B, 1, ct.byref(h)) == -1
+
+
+def test_create_checks_the_inlet_mode_against_the_lattice(lib):
+    # the adaptive inlet measures along x, y or z; a D2Q9 box has no z axis
+    from paper_1612_05404_amd import elbm, inputs
+    wl = inputs.paper_jet_2d(n=32, diameter=8, nozzle_len=6, wall=2)
+    B = (elbm.elbm_box * 1)(elbm.make_box(wl.params, wl.boxes[0]))
+    h = ct.c_void_p()
+    for mode, ok in ((elbm.INLET_ADAPTIVE_X, True), (elbm.INLET_ADAPTIVE_Y, True), (elbm.INLET_ADAPTIVE_Z, False),
+                     (elbm.INLET_NEIGHBOUR, True)):
+        P = elbm.make_params(wl.params.with_(inlet_mode=mode), elbm.STORAGE_F64)
+        st = lib.elbm_create(ct.byref(P), B, 1, ct.byref(h))
+        assert (st == 0) == ok, mode
+        if st == 0:
+            lib.elbm_destroy(h)
+            h = ct.c_void_p()

@@ -56,17 +56,54 @@ def compare(lat, i, o, tol, fields=("rhoA", "rhoB", "ux", "uy", "uz", "phi", "q"
     return errs
 
 
-def check_alpha(al, it, oal, oit, tol=1e-11, label="alpha"):
+def alpha_conditioning(fp, lat_id=0):
+    """Rounding allowance of alpha at each node from the conditioning of the
+    entropy balance (Eqs. entropic, H) in the populations themselves: alpha
+    depends on Delta = f_eq(f) - f, formed by cancellation, so a relative
+    change of eps in each f_p moves Delta_p by eps / |x_p| relative
+    (x = Delta / f) and alpha by about eps / x_rms, x_rms^2 = sum_p f_p x_p^2 /
+    sum_p f_p: near equilibrium (x_rms ~ 1e-5) two correct solvers differ in
+    the 11th digit.  Measured with the oracle's own solver under random 1-ulp
+    changes of f on the 2-D jet: at most 24 eps / x_rms; the allowance is
+    64 eps / x_rms (at most 1e-6).  fp: pulled populations [C][Q][...] of the step that
+    solved for alpha; returns [C][...]."""
+    import oracle as ora
+    c, w = ora.lattice(lat_id)
+    C, Q = fp.shape[0], fp.shape[1]
+    f = fp.reshape(C, Q, -1)
+    out = np.zeros((C, f.shape[2]))
+    for s in range(C):
+        fs = f[s]
+        rho = fs.sum(axis=0)
+        ok = rho > 0
+        with np.errstate(all="ignore"):
+            u = np.einsum("pa,pn->an", c.astype(np.float64), fs) / np.where(ok, rho, 1.0)
+            cu = np.einsum("pa,an->pn", c.astype(np.float64), u)
+            uu = (u * u).sum(axis=0)
+            feq = w[:, None] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
+            x = (feq - fs) / fs
+            xrms = np.sqrt((fs * x * x).sum(axis=0) / rho)
+            allow = np.minimum(64.0 * 2.220446049250313e-16 / xrms, 1e-6)
+        out[s] = np.where(ok & np.isfinite(allow), allow, 0.0)
+    return out.reshape((C,) + fp.shape[2:])
+
+
+def check_alpha(al, it, oal, oit, tol=1e-11, label="alpha", allowance=None):
     """Alpha of two solvers on the same states: the same fallback nodes, and
-    the largest relative difference over every node both solved within tol."""
+    the largest relative difference over every node both solved within tol
+    (plus, where given, a per-node allowance from the conditioning of the
+    entropy balance, alpha_conditioning)."""
     fb, ofb = it < 0, oit < 0
     both = (it >= 0) & (oit >= 0) & (oal > 0)
     err = np.abs(al - oal)[both] / oal[both]
     emax = float(err.max()) if err.size else 0.0
+    bar = tol + (allowance[both] if allowance is not None else 0.0)
+    worst = float((err / bar).max()) if err.size else 0.0
     _say(f"    {label}: max rel err {emax:.2e} over {int(both.sum())} solves; fallbacks {int(fb.sum())} / "
-         f"{int(ofb.sum())}; update counts equal {np.mean(it == oit):.4f}")
+         f"{int(ofb.sum())}; update counts equal {np.mean(it == oit):.4f}"
+         + (f"; largest error over its bar {worst:.3f}" if allowance is not None else ""))
     assert np.array_equal(fb, ofb), "fallback nodes differ"
-    assert emax <= tol, emax
+    assert worst <= 1.0 if allowance is not None else emax <= tol, emax
     return emax
 
 
