@@ -111,11 +111,12 @@ def cpu_baseline(inputs, budget_s: float = 12.0):
                                         f"{dt1:.1f} s"}}
 
 
-def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
+def ensemble_leg(elbm, inputs, learned, steps: int, trial: int, launch=None):
     """The batched ensemble: 256 independent periodic drop boxes (edges 24 to
     64, own radius, charge, field and Carreau exponent), FP32 populations,
-    learned starter; the autotuner's trials serve as warm-up, then `steps`
-    steps replayed as captured graphs of the chosen mapping."""
+    learned starter; the autotuner's trials serve as warm-up (or a given
+    launch mapping and `trial` warm-up steps), then `steps` steps replayed as
+    captured graphs of the chosen mapping."""
     import torch
     t0 = time.perf_counter()
     wl = inputs.ensemble()
@@ -125,7 +126,12 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
     lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
     if mode == "mlp":
         lat.mlp_set_weights(learned.load_weights())
-    best, ms = lat.autotune(trial)
+    if launch:
+        lat.set_launch(**launch)
+        lat.step(trial, record=False)
+        best, ms = launch, {}
+    else:
+        best, ms = lat.autotune(trial)
     lat.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -155,7 +161,7 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int):
             [(f"tile{t}", round(float(ms[t]), 4)) for t in range(4)]
             + [(f"remap{r}", round(float(ms[4 + r]), 4)) for r in range(2)]
             + [(f"prio{r}", round(float(ms[6 + r]), 4)) for r in range(2)]
-            + [(f"graph{g}", round(float(ms[8 + k]), 4)) for k, g in enumerate((2, 4, 8))])},
+            + [(f"graph{g}", round(float(ms[8 + k]), 4)) for k, g in enumerate((2, 4, 8))]) if len(ms) else None},
     }
 
 
@@ -181,6 +187,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--ensemble-steps", type=int, default=100)
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the batched-ensemble leg (with --launch: that mapping, no autotuner)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -199,6 +207,12 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+    if args.ensemble_only:
+        launch = parse_launch(args.launch) if args.launch else None
+        print(json.dumps({"ensemble": ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32,
+                                                   launch=launch)}), flush=True)
+        return
 
     t0 = time.perf_counter()
     wl = inputs.jet()

@@ -425,12 +425,26 @@ __device__ __forceinline__ double phi_of(double y, double l) {
 // evaluation at a + d would accept it, so it is returned without one.  The update count goes to `iters`, or -1 with the fallback
 // min(2, 0.99 a_max) when there is no root, Newton does not converge, or a
 // population is not positive (H undefined).
+// The set-up runs in two passes over the directions: x_p, max|x| and the
+// positivity bound, then the moments with L.  Between them the wave picks the
+// series degree: when every node of the wave has max|x| < QUIET_X (fluid near
+// equilibrium, most of a flow) the degree-5 truncation already meets the
+// acceptance bound and needs six moments instead of twelve, and its
+// logarithms take the Taylor path for small arguments (log1p_near0).
 // f: the node's 19 populations of one component (thread-private LDS column,
 // element p at offset p * BLK); xs: scratch for x (element p at p * XSTRIDE
 // in the wave's own LDS block).  Both keep the Newton loop rolled and the
 // register footprint small.  rho, u: FP64 moments of f.
 constexpr int XSTRIDE = 64;  // stride of a thread's x column in its wave's LDS block
 constexpr double SERIES_ACCEPT = 1.2;
+
+// State between the set-up pass and the Newton polish.
+struct AlphaSetup {
+  double L, amax, xmax, a;  // a: the starter so far
+  double M2;                // sum_p f_p x_p^2
+  int state;                // 0: Newton needed, 1: at equilibrium (2), 2: fallback, 3: the rule holds at a
+  bool want_learned;        // the learned starter would be used here
+};
 
 // Degree of the series starter's truncation: moments M_2 .. M_{D+1} (the last
 // one for the tail bound).  Measured on the e-field drop: 7 lets 23 % of the
@@ -441,99 +455,156 @@ constexpr int SERIES_DEG = 11;
 // The truncated series q(b) = L + sum_{k=2}^{D} (-1)^k b^(k-1) M_k / (k(k-1))
 // (g(b)/b without its tail) and its derivative in b, by Horner's rule
 // (M[k - 2] = M_k).
+template <int D>
 __device__ __forceinline__ double series_q(double b, double L, const double *M) {
-  constexpr int D = SERIES_DEG;
   double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D * (D - 1));
 #pragma unroll
   for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k * (k - 1)));
   return fma(b, h, L);
 }
+template <int D>
 __device__ __forceinline__ double series_dq(double b, const double *M) {
-  constexpr int D = SERIES_DEG;
   double h = ((D & 1) ? -M[D - 2] : M[D - 2]) / double(D);
 #pragma unroll
   for (int k = D - 1; k >= 2; --k) h = fma(b, h, ((k & 1) ? -M[k - 2] : M[k - 2]) / double(k));
   return h;
 }
 
-// State between the set-up pass and the Newton polish.
-struct AlphaSetup {
-  double L, amax, xmax, a;  // a: the starter so far
-  double M2;                // sum_p f_p x_p^2
-  int state;                // 0: Newton needed, 1: at equilibrium (2), 2: fallback, 3: the rule holds at a
-  bool want_learned;        // the learned starter would be used here
-};
+// ln(1 + y) for |y| < 1/32 by its Taylor series through y^12 (first dropped
+// term below 3e-19 relative, no reciprocal), log1p_fast elsewhere.
+__device__ __forceinline__ double log1p_near0(double y) {
+  if (fabs(y) < 0.03125) {
+    double h = -1.0 / 12.0;
+    h = fma(h, y, 1.0 / 11.0);
+    h = fma(h, y, -1.0 / 10.0);
+    h = fma(h, y, 1.0 / 9.0);
+    h = fma(h, y, -1.0 / 8.0);
+    h = fma(h, y, 1.0 / 7.0);
+    h = fma(h, y, -1.0 / 6.0);
+    h = fma(h, y, 1.0 / 5.0);
+    h = fma(h, y, -1.0 / 4.0);
+    h = fma(h, y, 1.0 / 3.0);
+    h = fma(h, y, -0.5);
+    return fma(h * y, y, y);
+  }
+  return log1p_fast(y);
+}
+
+// Degree of the series starter on quiet waves (every node with max|x| below
+// QUIET_X): there the degree-5 truncation already meets the acceptance bound
+// at b ~ 2 (tail b^5 M_6 / 30 <= 2^3 max|x|^4 b^2 M_2 / 30), so its six
+// moments replace the twelve of SERIES_DEG.
+constexpr int QUIET_DEG = 5;
+constexpr double QUIET_X = 5e-4;
+
+// Moments M_2 .. M_{D+1} of one node from its x and f columns and the
+// entropy term L = sum_p Delta_p ln(f_p / (w_p rho)) (fixed order p = 0..Q-1;
+// Delta_p recomputed exactly as in the set-up pass).  NEAR0: the logarithm
+// takes its Taylor series where |y| < 1/32.
+template <typename Lat, typename T, int D, bool NEAR0>
+__device__ __forceinline__ double series_moments(const T *f, const double *xs, double *M, double rho, double irho,
+                                                 double ux, double uy, double uz, double uu) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) M[k] = 0.0;
+  double L = 0.0;
+#pragma unroll
+  for (int p = 0; p < Lat::Q; ++p) {
+    const double fp = double(f[p * BLK]);
+    const double x = xs[p * XSTRIDE];
+    double t = fp * x * x;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      M[k] += t;
+      t *= x;
+    }
+    const double wr = Lat::w(p) * rho;
+    const double d = feq<Lat, double>(p, rho, ux, uy, uz, uu) - fp;
+    const double y = (fp - wr) * (irho * (1.0 / Lat::w(p)));
+    L += d * (NEAR0 ? log1p_near0(y) : log1p_fast(y));
+  }
+  return L;
+}
+
+// Newton on the degree-D truncated series from 2 (no logarithms); sets
+// st.a / st.state / st.want_learned as the series starter decides.
+template <int D>
+__device__ __forceinline__ void series_start(AlphaSetup &st, const double *M, double L, double amax,
+                                             double xmax, int guess, double rtol) {
+  double b = 2.0;
+#pragma unroll 1
+  for (int k = 0; k < 6; ++k) {
+    const double q = series_q<D>(b, L, M);
+    const double dq = series_dq<D>(b, M);
+    if (!(dq > 0.0)) break;
+    b -= q / dq;
+  }
+  if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
+    st.a = b;
+    const double bx = b * xmax;
+    if (bx < 0.5) {
+      const double qb = series_q<D>(b, L, M);
+      double bd = b;  // b^D
+#pragma unroll
+      for (int k = 1; k < D; ++k) bd *= b;
+      const double tail = bd * M[D - 1] / (double((D + 1) * D) * (1.0 - bx));
+      if (b * (fabs(qb) + tail) <= 0.25 * rtol * b * b * M[0] * (1.0 - bx / 3.0)) st.state = 3;
+    }
+  } else {
+    st.want_learned = guess == ELBM_GUESS_MLP;
+  }
+}
+
 
 template <typename Lat, typename T>
 __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double rho, double ux, double uy,
                                                   double uz, int guess, double rtol) {
   const double uu = ux * ux + uy * uy + uz * uz;
   const double irho = rcp_nr(rho);
-  double xmax = 0.0, xmin = 0.0, L = 0.0;
-  double M[SERIES_DEG];  // M[k - 2] = M_k, k = 2 .. SERIES_DEG + 1
-#pragma unroll
-  for (int k = 0; k < SERIES_DEG; ++k) M[k] = 0.0;
+  double xmax = 0.0, xmin = 0.0;
   bool nonpos = false;
-#pragma unroll  // fully: the lattice vectors fold into the equilibria (3 % faster than by 4)
+#pragma unroll  // fully: the lattice vectors fold into the equilibria
   for (int p = 0; p < Lat::Q; ++p) {
     const double fp = double(f[p * BLK]);
-    const double wr = Lat::w(p) * rho;
     const double d = feq<Lat, double>(p, rho, ux, uy, uz, uu) - fp;
     const double x = d * rcp_nr(fp);
     nonpos |= !(fp > 0.0);
     xs[p * XSTRIDE] = x;
     xmax = fmax(xmax, fabs(x));
     xmin = fmin(xmin, x);
-    L += d * log1p_fast((fp - wr) * (irho * (1.0 / Lat::w(p))));
-    double t = fp * x * x;
-#pragma unroll
-    for (int k = 0; k < SERIES_DEG; ++k) {
-      M[k] += t;
-      t *= x;
-    }
   }
   // top of the positivity interval, min over x_p < 0 of -1/x_p = -1/min x
   const double amax = xmin < 0.0 ? -rcp_nr(xmin) : INFINITY;
   AlphaSetup st;
-  st.M2 = M[0];
-  st.L = L;
+  st.L = 0.0;
   st.amax = amax;
   st.xmax = xmax;
   st.a = 2.0;
   st.want_learned = false;
+  st.M2 = 0.0;
   if (nonpos) {  // H(f) is undefined for a non-positive population
     st.state = 2;
     return st;
   }
+  const bool series = guess == ELBM_GUESS_SERIES || guess == ELBM_GUESS_MLP;
+  // the moments the series starter and the Taylor bounds need, at the
+  // degree of the wave: quiet waves (every active lane near equilibrium)
+  // take the short truncation
+  double M[SERIES_DEG];
+  const bool quiet = series && __all(xmax < QUIET_X);
+  double L;
+  if (quiet) L = series_moments<Lat, T, QUIET_DEG, true>(f, xs, M, rho, irho, ux, uy, uz, uu);
+  else if (series) L = series_moments<Lat, T, SERIES_DEG, false>(f, xs, M, rho, irho, ux, uy, uz, uu);
+  else L = series_moments<Lat, T, 1, false>(f, xs, M, rho, irho, ux, uy, uz, uu);
+  st.L = L;
+  st.M2 = M[0];
   if (xmax < 1e-12) {
     st.state = 1;
     return st;
   }
   st.state = L < 0.0 ? 0 : 2;
-  if (st.state == 0 && (guess == ELBM_GUESS_SERIES || guess == ELBM_GUESS_MLP)) {
-    // Newton on the truncated series from 2 (no logarithms)
-    double b = 2.0;
-#pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
-      const double q = series_q(b, L, M);
-      const double dq = series_dq(b, M);
-      if (!(dq > 0.0)) break;
-      b -= q / dq;
-    }
-    if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
-      st.a = b;
-      const double bx = b * xmax;
-      if (bx < 0.5) {
-        const double qb = series_q(b, L, M);
-        double bd = b;  // b^SERIES_DEG
-#pragma unroll
-        for (int k = 1; k < SERIES_DEG; ++k) bd *= b;
-        const double tail = bd * M[SERIES_DEG - 1] / (double((SERIES_DEG + 1) * SERIES_DEG) * (1.0 - bx));
-        if (b * (fabs(qb) + tail) <= 0.25 * rtol * b * b * M[0] * (1.0 - bx / 3.0)) st.state = 3;
-      }
-    } else {
-      st.want_learned = guess == ELBM_GUESS_MLP;
-    }
+  if (st.state == 0 && series) {
+    if (quiet) series_start<QUIET_DEG>(st, M, L, amax, xmax, guess, rtol);
+    else series_start<SERIES_DEG>(st, M, L, amax, xmax, guess, rtol);
   }
   return st;
 }
