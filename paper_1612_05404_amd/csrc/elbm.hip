@@ -57,6 +57,10 @@ struct elbm_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool bound = false;
   bool any_gauge = false;
+  // SOR half sweeps with one thread per node pair: every box has an even x
+  // extent and at least 2^20 nodes (measured faster there, slower on small
+  // boxes where the pair's halved parallelism matters more)
+  bool sor_pairs = false;
   int parity = 0;  // which population buffer is current (0: fa region)
   std::string err;
   // device timing: ELBM_NPHASES + 1 events per timed step, recycled
@@ -287,9 +291,15 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
   // the last one, which recorded steps always take (diagnostics)
   const int nsw = c->P.sor_sweeps, every = c->P.sor_check_every;
   const bool tol = c->P.sor_tol > 0.0, checks = tol && every > 0;
+  const dim3 pgrid((c->nblocks + 1) / 2);
   for (int sw = 1; sw <= nsw; ++sw) {
-    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0, (int)checks);
-    hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1, (int)checks);
+    if (c->sor_pairs) {
+      hipLaunchKernelGGL((k_sor_pair<T, F>), pgrid, blk, 0, c->stream, a, 0, (int)checks);
+      hipLaunchKernelGGL((k_sor_pair<T, F>), pgrid, blk, 0, c->stream, a, 1, (int)checks);
+    } else {
+      hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 0, (int)checks);
+      hipLaunchKernelGGL((k_sor<T, F>), grid, blk, 0, c->stream, a, 1, (int)checks);
+    }
     if (checks && sw % every == 0 && sw < nsw) {
       hipLaunchKernelGGL((k_residual<T, F>), grid, blk, 0, c->stream, a, 1);
       hipLaunchKernelGGL(k_res_box, dim3(nb), blk, 0, c->stream, a.boxes, (const double *)a.res_part, a.scal, a.cnt,
@@ -588,6 +598,9 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   }
   c->Ntot = off;
   c->nblocks = blk0;
+  c->sor_pairs = true;
+  for (const auto &x : c->boxes)
+    if ((x.nx & 1) || (int64_t)x.nx * x.ny * x.nz < ((int64_t)1 << 20)) c->sor_pairs = false;
   for (int s = 1; s < NTILE_SHAPES; ++s) {
     int t0 = 0;
     for (int b = 0; b < nboxes; ++b) {

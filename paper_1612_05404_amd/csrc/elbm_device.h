@@ -536,7 +536,9 @@ __device__ __forceinline__ void series_start(AlphaSetup &st, const double *M, do
     const double q = series_q<D>(b, L, M);
     const double dq = series_dq<D>(b, M);
     if (!(dq > 0.0)) break;
-    b -= q / dq;
+    const double step = q / dq;
+    b -= step;
+    if (fabs(step) <= 1e-15 * b) break;  // converged: further updates move b by rounding only
   }
   if (b > 0.0 && b < amax && b * xmax < SERIES_ACCEPT) {
     st.a = b;

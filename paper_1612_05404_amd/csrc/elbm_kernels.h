@@ -286,6 +286,54 @@ __global__ __launch_bounds__(BLK) void k_sor(Ptrs<T, F> a, int colour, int skip_
   a.phi[nd.g] = (F(1) - om) * pc + om * (Bs - rhs) / A;
 }
 
+// The same half sweep with one thread per pair of x-consecutive nodes (every
+// box has an even x extent): the thread updates the pair's node of this
+// colour, so half the waves run and none idles on the other colour.  Each
+// wave's 128 nodes lie in one 256-node block (a box starts at a multiple of
+// 256 nodes), so the block and its box record are wave-uniform.  Same
+// arithmetic per node as k_sor: bit-identical potentials.
+template <typename T, typename F>
+__global__ __launch_bounds__(BLK) void k_sor_pair(Ptrs<T, F> a, int colour, int skip_converged) {
+  const int pb = logical_block((a.nblocks + 1) >> 1, a.remap);  // 512-node block
+  const int blk = __builtin_amdgcn_readfirstlane(2 * pb + (threadIdx.x >> 7));
+  field_chain_priority(a.prio);
+  if (blk >= a.nblocks) return;
+  const int bb = a.block_box[blk];
+  const BoxDev B = a.boxes[bb];
+  const int64_t g0 = (int64_t)blk * BLK + 2 * (threadIdx.x & 127);
+  const int n0 = (int)(g0 - B.off);
+  if (n0 >= B.n) return;
+  if (skip_converged && a.scal[(int64_t)bb * NSCAL + 7] != 0.0) return;
+  const int x0 = n0 % B.nx, r = n0 / B.nx, y = r % B.ny, z = r / B.ny;
+  const int sh = ((x0 + y + z) & 1) != colour ? 1 : 0;
+  const int x = x0 + sh, n = n0 + sh;
+  const int64_t g = g0 + sh;
+  const uint8_t tt = a.type[g];
+  const F rc = a.rho[g], pc = a.phi[g], rhs = a.rhs[g];
+  F rn[6], pn[6];
+  unsigned inside = 0u;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int m = nbr(B, x, y, z, kFace[f][0], kFace[f][1], kFace[f][2]);
+    if (m >= 0) inside |= 1u << f;
+    const int64_t gm = B.off + (m >= 0 ? m : n);
+    rn[f] = a.rho[gm];
+    pn[f] = a.phi[gm];
+  }
+  if (tt & B_DIRICHLET) return;
+  const F ec = F(1) + rc;
+  F A = F(0), Bs = F(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (!((inside >> f) & 1u)) continue;
+    const F ef = F(0.5) * (ec + (F(1) + rn[f]));
+    A += ef;
+    Bs += ef * pn[f];
+  }
+  const F om = F(B.omega);
+  a.phi[g] = (F(1) - om) * pc + om * (Bs - rhs) / A;
+}
+
 // Poisson residual of every unknown node in FP64,
 //   r = sum_faces eps_f (phi_nb - phi) - rhs   (faces leaving the box skipped),
 // and the block maxima of |r| and |rhs|.  Boxes whose solve already met its

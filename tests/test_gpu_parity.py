@@ -421,3 +421,13 @@ def test_nonfinite_is_reported(elbm):
     with pytest.raises(elbm.ElbmError) as e:
         lat.sync()
     assert e.value.status == elbm.ELBM_ENONFINITE
+
+
+def test_large_box_fp64_parity(elbm):
+    # A box of 2^20 nodes (the e-field drop's walls and electrodes at
+    # 128x128x64), where the Poisson half sweeps run one thread per node pair:
+    # FP64, 6 steps, every field against the oracle at the FP64 bar.
+    wl = inputs.efield_drop(nx=128, ny=128, nz=64)
+    p = wl.params.with_(sor_sweeps=9)
+    lat, (o,) = run_both(elbm, p, wl.boxes, "f64", 6, "e-field drop 128x128x64 (pair sweeps)")
+    compare(lat, 0, o, 1e-12)
