@@ -193,7 +193,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
-              f"the update has no multi-GPU path in this build", file=sys.stderr)
+              f"the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
