@@ -759,7 +759,7 @@ __device__ __forceinline__ double rsq_nr(double d) {
 }
 
 template <typename R>
-__device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
+__device__ R sym3_norm2_jacobi(R a00, R a11, R a22, R a01, R a02, R a12) {
   R a[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
   const R tiny = sizeof(R) == 8 ? R(1e-24) : R(1e-14);
   for (int sweep = 0; sweep < 10; ++sweep) {
@@ -799,6 +799,54 @@ __device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
     }
   }
   return fmax(fabs(a[0][0]), fmax(fabs(a[1][1]), fabs(a[2][2])));
+}
+
+// The same 2-norm from the characteristic cubic: with q = tr A / 3,
+// B = (A - q I) / p, p^2 = tr((A - q I)^2) / 6, the eigenvalues are
+// q + 2 p cos(phi + 2 pi k / 3), phi = acos(det B / 2) / 3 in [0, pi/3].  c =
+// cos(phi) is the largest root of 4 c^3 - 3 c = r, r = det B / 2: an FP32
+// start from acos / cos, then two Newton steps in R; sin(phi) =
+// sqrt(1 - c^2).  The largest eigenvalue is q + 2 p c, the smallest
+// q - p (c + sqrt3 sin(phi)), the middle one 3q minus those.  Near a double
+// eigenvalue (|r| -> 1) the cubic's roots lose digits (error ~ eps /
+// sqrt(1 - r^2)), so for 1 - |r| < 5e-5 the Jacobi iteration above answers.
+// Elsewhere the result is within ~1e-14 relative of the exact 2-norm.
+template <typename R>
+__device__ R sym3_norm2(R a00, R a11, R a22, R a01, R a02, R a12) {
+  const R p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const R q = (a00 + a11 + a22) * R(1.0 / 3.0);
+  const R b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+  const R p2 = b00 * b00 + b11 * b11 + b22 * b22 + R(2) * p1;
+  if (!(p2 > R(0))) return fabs(q);
+  R p, ip;
+  if constexpr (sizeof(R) == 8) {
+    const double h = p2 * (1.0 / 6.0);
+    const double rs = rsq_nr(h);
+    p = h * rs;
+    ip = rs;
+  } else {
+    p = sqrt(p2 * R(1.0 / 6.0));
+    ip = R(1) / p;
+  }
+  const R c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
+  const R r = R(0.5) * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02));
+  if (!(fabs(r) < R(1) - R(5e-5))) return sym3_norm2_jacobi<R>(a00, a11, a22, a01, a02, a12);
+  R c = R(cosf(acosf(float(r)) * (1.0f / 3.0f)));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const R g = (R(4) * c * c - R(3)) * c - r;
+    const R dg = R(12) * c * c - R(3);
+    if constexpr (sizeof(R) == 8) c -= g * rcp_nr(dg);
+    else c -= g / dg;
+  }
+  const R s2 = R(1) - c * c;
+  R sn;
+  if constexpr (sizeof(R) == 8) sn = s2 > 0.0 ? s2 * rsq_nr(s2) : 0.0;
+  else sn = sqrt(fmax(s2, R(0)));
+  const R l1 = q + R(2) * p * c;
+  const R l3 = q - p * (c + R(1.7320508075688772935) * sn);
+  const R l2 = R(3) * q - l1 - l3;
+  return fmax(fabs(l1), fmax(fabs(l2), fabs(l3)));
 }
 
 // Shear rate of Eq. strain2: the root of h(g) = rho (2 nu(g) + c_s^2) g - alpha Pi

@@ -635,7 +635,7 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         // (none along z on D2Q9, where every c_z and u_z vanish), so only f is
         // summed
         double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
-#pragma unroll 1
+#pragma unroll  // fully: the lattice vectors fold and the LDS reads issue together
         for (int p = 0; p < Lat::Q; ++p) {
           const double d = double(f[p * BLK]);
           P00 += d * double(Lat::cx[p] * Lat::cx[p]);
