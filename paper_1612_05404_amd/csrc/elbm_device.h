@@ -871,8 +871,12 @@ __device__ R shear_rate(R Pn, R rho, R alpha, R nu0, R ninf, R lam, R n) {
     if (h > R(0)) hi = g; else lo = g;
     const R dh = rho * (R(2) * ninf + R(CS2) + R(2) * (nu0 - ninf) * e * (R(1) + n * lg * lg));
     R gn = g - h / dh;
-    if (!(gn >= lo && gn <= hi)) gn = R(0.5) * (lo + hi);
+    const bool newton = gn >= lo && gn <= hi;
+    if (!newton) gn = R(0.5) * (lo + hi);
     if (fabs(gn - g) <= tol * g || hi - lo <= tol * R(0.1) * hi) return gn;
+    // a Newton step this small is in the quadratic regime: the next update
+    // would be below the tolerance (relative 1e-16), so gn is returned now
+    if (sizeof(R) == 8 && newton && fabs(gn - g) <= R(1e-8) * g) return gn;
     g = gn;
   }
   return g;

@@ -594,6 +594,8 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         jz += double(Lat::cz[p]) * dv;
       }
     }
+    // divisions, not one reciprocal: every instantiation (plain, learned)
+    // then forms the same velocity, so starters agree on the same state
     const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
     // ---- alpha set-up at the component's own velocity (FP64)
     AlphaSetup st{};
@@ -766,7 +768,8 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       jy += double(Lat::cy[p]) * dv;
       jz += double(Lat::cz[p]) * dv;
     }
-    const double ux = jx / dr, uy = jy / dr, uz = jz / dr;
+    const double ird = rcp_nr(dr);  // one reciprocal for the three components
+    const double ux = jx * ird, uy = jy * ird, uz = jz * ird;
     const double uu = ux * ux + uy * uy + uz * uz;
     drt += dr;
     const F ps = a.psi[nd.g * C + s];
@@ -783,7 +786,7 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
     const double ab = a.ab[(int64_t)s * a.N + nd.g];
     // ---- exact-difference source (Eq. add): with v = u + F/rho,
     // f_eq(v) - f_eq(u) = w rho [3 c.du + 4.5 (c.du)(c.(u+v)) - 1.5 du.(u+v)]
-    const double dx_ = double(Fs[0]) / dr, dy_ = double(Fs[1]) / dr, dz_ = double(Fs[2]) / dr;
+    const double dx_ = double(Fs[0]) * ird, dy_ = double(Fs[1]) * ird, dz_ = double(Fs[2]) * ird;
     const double sx = 2.0 * ux + dx_, sy = 2.0 * uy + dy_, sz = 2.0 * uz + dz_;
     const double ds = dx_ * sx + dy_ * sy + dz_ * sz;
 #pragma unroll
