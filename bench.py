@@ -111,27 +111,26 @@ def cpu_baseline(inputs, budget_s: float = 12.0):
                                         f"{dt1:.1f} s"}}
 
 
-def ensemble_leg(elbm, inputs, learned, steps: int, trial: int, launch=None):
-    """The batched ensemble: 256 independent periodic drop boxes (edges 24 to
-    64, own radius, charge, field and Carreau exponent), FP32 populations,
-    learned starter; the autotuner's trials serve as warm-up (or a given
-    launch mapping and `trial` warm-up steps), then `steps` steps replayed as
-    captured graphs of the chosen mapping."""
+# steps the autotuner advances the state (22 trials of 32 steps and 60 graph
+# warm-up steps; elbm_autotune)
+AUTOTUNE_STEPS = 22 * 32 + 60
+
+
+def _ensemble_run(elbm, learned, wl, guess, launch, warm, steps):
+    """One starter on the ensemble from its initial state: `warm` untimed
+    steps at `launch` (None: the autotuner chooses it, its trials being the
+    warm-up), then `steps` timed steps; returns the mapping, the autotuner's
+    times, ms per step and the Newton updates per solved node-component."""
     import torch
-    t0 = time.perf_counter()
-    wl = inputs.ensemble()
-    mode = "mlp" if os.path.exists(learned.WEIGHTS) else "series"
-    print(f"[bench] ensemble: {len(wl.boxes)} boxes, {wl.nodes} nodes, guess {mode} "
-          f"(inputs {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=mode)
-    if mode == "mlp":
+    lat = elbm.Lattice(wl.params, wl.boxes, wl.dtype, device="cuda:0", alpha_guess=guess)
+    if guess == "mlp":
         lat.mlp_set_weights(learned.load_weights())
     if launch:
         lat.set_launch(**launch)
-        lat.step(trial, record=False)
+        lat.step(warm, record=False)
         best, ms = launch, {}
     else:
-        best, ms = lat.autotune(trial)
+        best, ms = lat.autotune(32)
     lat.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -145,18 +144,49 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int, launch=None):
     iters = sum(d["mean_newton_iters"] * (d["n_collisions"] - d["n_fallback"]) for d in diags)
     nfb = sum(d["n_fallback"] for d in diags)
     lat.close()
-    edges = sorted({b.nx for b in wl.boxes})
-    mlups = wl.nodes * steps / dt / 1e6
+    return best, ms, dt / steps * 1e3, iters / max(ncol - nfb, 1)
+
+
+def ensemble_leg(elbm, inputs, learned, steps: int, trial: int, launch=None, compare=("series", "standard")):
+    """The batched ensemble: 256 independent periodic drop boxes (edges 24 to
+    64, own radius, charge, field and Carreau exponent), FP32 populations,
+    learned starter; the autotuner's trials serve as warm-up (or a given
+    launch mapping and `trial` warm-up steps), then `steps` steps replayed as
+    captured graphs of the chosen mapping.  Each starter in `compare` then
+    runs the same number of steps from the same initial state at that
+    mapping and is timed over the same window."""
+    t0 = time.perf_counter()
+    wl = inputs.ensemble()
+    mode = "mlp" if os.path.exists(learned.WEIGHTS) else "series"
+    print(f"[bench] ensemble: {len(wl.boxes)} boxes, {wl.nodes} nodes, guess {mode} "
+          f"(inputs {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    warm = trial if launch else AUTOTUNE_STEPS
+    best, ms, ms_step, iters = _ensemble_run(elbm, learned, wl, mode, launch, trial, steps)
     sb = step_bytes_per_node(4, wl.params.ncomp, wl.params.sor_sweeps)
+
+    def rate(t):
+        return wl.nodes / (t * 1e-3) / 1e6
+
+    runs = {mode: {"mlups": round(rate(ms_step), 3), "ms_per_step": round(ms_step, 4),
+                   "mean_newton_iters": round(iters, 4)}}
+    for g in compare:
+        if not g or g == mode:
+            continue
+        print(f"[bench] ensemble: starter {g}, {warm} + {steps} steps", file=sys.stderr, flush=True)
+        _, _, t, it = _ensemble_run(elbm, learned, wl, g, best, warm, steps)
+        runs[g] = {"mlups": round(rate(t), 3), "ms_per_step": round(t, 4), "mean_newton_iters": round(it, 4)}
+    edges = sorted({b.nx for b in wl.boxes})
     return {
         "workload": f"ensemble: {len(wl.boxes)} periodic drop boxes, edges {edges}, FP32 populations, FP64 alpha",
         "nodes": wl.nodes,
         "steps": steps,
-        "mlups": round(mlups, 3),
-        "ms_per_step": round(dt / steps * 1e3, 4),
-        "hbm_frac": round(sb * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+        "start_step": warm + 1,
+        "mlups": round(rate(ms_step), 3),
+        "ms_per_step": round(ms_step, 4),
+        "hbm_frac": round(sb * rate(ms_step) * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
         "alpha_guess": mode,
-        "mean_newton_iters": round(iters / max(ncol - nfb, 1), 4),
+        "mean_newton_iters": round(iters, 4),
+        "starters": runs,
         "autotune": {"best": best, "ms_per_step": dict(
             [(f"tile{t}", round(float(ms[t]), 4)) for t in range(4)]
             + [(f"remap{r}", round(float(ms[4 + r]), 4)) for r in range(2)]
@@ -187,6 +217,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--ensemble-steps", type=int, default=100)
+    ap.add_argument("--ensemble-starters", default="series,standard",
+                    help="starters timed beside the learned one on the ensemble ('' for none)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="run only the batched-ensemble leg (with --launch: that mapping, no autotuner)")
     args = ap.parse_args()
@@ -211,7 +243,8 @@ def main():
     if args.ensemble_only:
         launch = parse_launch(args.launch) if args.launch else None
         print(json.dumps({"ensemble": ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32,
-                                                   launch=launch)}), flush=True)
+                                                   launch=launch, compare=args.ensemble_starters.split(","))}),
+              flush=True)
         return
 
     t0 = time.perf_counter()
@@ -393,7 +426,8 @@ def main():
                       "sor_residual_rel": round(form_diag["sor_residual"] / max(form_diag["sor_scale"], 1e-300), 6)},
     }
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32)
+        out["ensemble"] = ensemble_leg(elbm, inputs, learned, args.ensemble_steps, trial=32,
+                                       compare=args.ensemble_starters.split(","))
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inputs)

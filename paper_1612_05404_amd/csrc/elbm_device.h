@@ -190,22 +190,26 @@ __device__ __forceinline__ void decode(const P &a, Node &nd) {
   nd.z = r / nd.B.ny;
 }
 
-// local index of r + (dx,dy,dz), wrapping periodic axes; -1 outside the box
-__device__ __forceinline__ int nbr(const BoxDev &B, int x, int y, int z, int dx, int dy, int dz) {
-  int xx = x + dx, yy = y + dy, zz = z + dz;
-  if (xx < 0 || xx >= B.nx) {
-    if (!B.per[0]) return -1;
-    xx = xx < 0 ? xx + B.nx : xx - B.nx;
-  }
-  if (yy < 0 || yy >= B.ny) {
-    if (!B.per[1]) return -1;
-    yy = yy < 0 ? yy + B.ny : yy - B.ny;
-  }
-  if (zz < 0 || zz >= B.nz) {
-    if (!B.per[2]) return -1;
-    zz = zz < 0 ? zz + B.nz : zz - B.nz;
-  }
-  return xx + B.nx * (yy + B.ny * zz);
+// One axis of nbr: the coordinate c + d wrapped once by the extent n where
+// the axis is periodic; ok cleared where it leaves a closed axis.
+__host__ __device__ __forceinline__ int wrap_axis(int c, int d, int n, int per, bool &ok) {
+  const int v = c + d;
+  if (d == 0) return v;  // a lattice offset: resolved at compile time in the unrolled loops
+  const bool lo = v < 0, hi = v >= n;
+  ok &= !(lo | hi) | (per != 0);
+  return lo ? v + n : hi ? v - n : v;
+}
+
+// local index of r + (dx,dy,dz), wrapping periodic axes; -1 outside the box.
+// Selects only, no branches: in the unrolled stencil loops a branch per
+// direction and axis cost more than the loads it guarded.
+__host__ __device__ __forceinline__ int nbr(const BoxDev &B, int x, int y, int z, int dx, int dy, int dz) {
+  bool ok = true;
+  const int xx = wrap_axis(x, dx, B.nx, B.per[0], ok);
+  const int yy = wrap_axis(y, dy, B.ny, B.per[1], ok);
+  const int zz = wrap_axis(z, dz, B.nz, B.per[2], ok);
+  const int m = xx + B.nx * (yy + B.ny * zz);
+  return ok ? m : -1;
 }
 
 // --------------------------------------------------------- reductions
