@@ -586,6 +586,7 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
     d.nx = x.nx; d.ny = x.ny; d.nz = x.nz; d.n = (int32_t)n;
     for (int k = 0; k < 3; ++k) { d.per[k] = x.periodic[k] ? 1 : 0; d.E[k] = x.E_ext[k]; }
     d.Q_b = x.Q_b; d.Q_s = x.Q_s; d.n_flow = x.n_flow; d.omega = x.sor_omega;
+    d.rnx = 1.0 / x.nx; d.rny = 1.0 / x.ny;
     const int nblk = (int)((n + BLK - 1) / BLK);
     d.first_block = blk0;
     d.nblocks = nblk;

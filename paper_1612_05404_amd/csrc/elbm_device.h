@@ -60,6 +60,7 @@ struct BoxDev {
   int32_t first_block, nblocks, n_unknown, pad;
   double E[3];
   double Q_b, Q_s, n_flow, omega;
+  double rnx, rny;  // 1/nx, 1/ny (FP64) for the index division of div_extent
 };
 
 struct Model {
@@ -175,6 +176,12 @@ __device__ __forceinline__ void decode_tile(const P &a, Node &nd) {
   nd.g = nd.B.off + nd.n;
 }
 
+// t / n for 0 <= t < 2^30 and an extent n >= 1 from rn = 1/n (FP64), in
+// place of an integer division: (t + 1/2)/n lies at least 1/(2n) from an
+// integer, and the two roundings (of 1/n and of the product) move it by at
+// most (t + 1/2)/n * 2^-52 < 2^-22/n, so the truncation is the exact quotient.
+__host__ __device__ __forceinline__ int div_extent(int t, double rn) { return (int)((double(t) + 0.5) * rn); }
+
 template <typename P>
 __device__ __forceinline__ void decode(const P &a, Node &nd) {
   nd.blk = logical_block(a.nblocks, a.remap);
@@ -184,10 +191,10 @@ __device__ __forceinline__ void decode(const P &a, Node &nd) {
   nd.n = (int)(nd.g - nd.B.off);
   nd.live = nd.n < nd.B.n;
   const int t = nd.live ? nd.n : 0;
-  nd.x = t % nd.B.nx;
-  const int r = t / nd.B.nx;
-  nd.y = r % nd.B.ny;
-  nd.z = r / nd.B.ny;
+  const int r = div_extent(t, nd.B.rnx);
+  nd.x = t - r * nd.B.nx;
+  nd.z = div_extent(r, nd.B.rny);
+  nd.y = r - nd.z * nd.B.ny;
 }
 
 // One axis of nbr: the coordinate c + d wrapped once by the extent n where

@@ -304,7 +304,8 @@ __global__ __launch_bounds__(BLK) void k_sor_pair(Ptrs<T, F> a, int colour, int 
   const int n0 = (int)(g0 - B.off);
   if (n0 >= B.n) return;
   if (skip_converged && a.scal[(int64_t)bb * NSCAL + 7] != 0.0) return;
-  const int x0 = n0 % B.nx, r = n0 / B.nx, y = r % B.ny, z = r / B.ny;
+  const int r = div_extent(n0, B.rnx), z = div_extent(r, B.rny);
+  const int x0 = n0 - r * B.nx, y = r - z * B.ny;
   const int sh = ((x0 + y + z) & 1) != colour ? 1 : 0;
   const int x = x0 + sh, n = n0 + sh;
   const int64_t g = g0 + sh;
