@@ -197,9 +197,10 @@ def ensemble_leg(elbm, inputs, learned, steps: int, trial: int, launch=None, com
 
 def parse_launch(text):
     v = [int(x) for x in text.split(",")]
-    if len(v) not in (3, 4):
-        sys.exit(f"--launch takes remap,graph_steps,tile[,sweep_priority], got {text!r}")
-    return {"xcd_remap": v[0], "graph_steps": v[1], "tile": v[2], "sweep_priority": v[3] if len(v) == 4 else 0}
+    if len(v) not in (3, 4, 5):
+        sys.exit(f"--launch takes remap,graph_steps,tile[,sweep_priority[,stencil_lds]], got {text!r}")
+    return {"xcd_remap": v[0], "graph_steps": v[1], "tile": v[2], "sweep_priority": v[3] if len(v) >= 4 else 0,
+            "stencil_lds": v[4] if len(v) == 5 else 0}
 
 
 def main():
@@ -212,7 +213,8 @@ def main():
     ap.add_argument("--starters", default="series,mlp,standard",
                     help="alpha starters to time (the first is the reported value)")
     ap.add_argument("--launch", default=None,
-                    help="launch mapping remap,graph_steps,tile[,sweep_priority] for every starter (no autotuner)")
+                    help="launch mapping remap,graph_steps,tile[,sweep_priority[,stencil_lds]] for every starter "
+                         "(no autotuner)")
     ap.add_argument("--phase-steps", type=int, default=50, help="steps of the per-phase event timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")

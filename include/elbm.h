@@ -42,13 +42,14 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 6u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
+#define ELBM_ABI_VERSION 7u  /* 2: fluid-wall coupling matrix Gw[2][2]; alpha phase in the timing;
                                  3: sweep_priority in elbm_launch;
                                  4: Poisson stop rule and residual, strict error flags, Halley
                                     iteration, electric force and solver fields in elbm_diag;
                                  5: the lattice (D3Q19 or the paper's D2Q9) in elbm_params;
                                  6: the adaptive jet inlet (inlet_mode, NOZZLE nodes, the
-                                    measured mean velocity in elbm_diag) */
+                                    measured mean velocity in elbm_diag);
+                                 7: stencil_lds in elbm_launch */
 
 typedef struct elbm_ctx elbm_ctx;
 
@@ -363,14 +364,21 @@ elbm_status elbm_alpha_samples(elbm_ctx *ctx, int32_t box, void *dFeat, void *dT
  * waves of the field chain after the densities (gradient, interface, charge,
  * SOR sweeps, gauge, E field), which runs on the bound stream while the alpha
  * kernel runs on the library's second stream: it helps when that chain is
- * the longer of the two branches, 0 (hardware default) when alpha is.  None changes any
- * result: per-node arithmetic and the order of every reduction are the same
- * under all mappings. */
+ * the longer of the two branches, 0 (hardware default) when alpha is.
+ * stencil_lds: 1 stages the neighbour values of the density-gradient and
+ * E-field stencils in LDS (each 256-node block loads, for the z offsets -1, 0,
+ * +1 of the stencil, its own index range widened by nx + 1 nodes on either
+ * side, then reads those slabs in place of per-direction loads); it needs the
+ * slabs of the widest box, (D3Q19: 3, D2Q9: 1) x (256 + 2 (nx + 1)) field
+ * values, within 32 KB, else ELBM_EINVAL.  0 (default) reads each neighbour
+ * from memory.  None changes any result: per-node arithmetic and the order
+ * of every reduction are the same under all mappings. */
 typedef struct elbm_launch {
   int32_t xcd_remap;
   int32_t graph_steps;
   int32_t tile;
   int32_t sweep_priority;
+  int32_t stencil_lds;
 } elbm_launch;
 #define ELBM_TUNE_CANDIDATES 11
 /* Sets / reads the launch mapping (synchronises the bound stream; drops the

@@ -22,6 +22,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -61,6 +62,12 @@ struct elbm_ctx {
   // extent and at least 2^20 nodes (measured faster there, slower on small
   // boxes where the pair's halved parallelism matters more)
   bool sor_pairs = false;
+  // LDS slabs for the gradient and E-field stencils (launch option
+  // stencil_lds): slab stride (0: they do not fit) and the dynamic LDS of one
+  // block
+  int slab_lmax = 0;
+  size_t slab_bytes = 0;
+  bool slabs = false;
   int parity = 0;  // which population buffer is current (0: fa region)
   std::string err;
   // device timing: ELBM_NPHASES + 1 events per timed step, recycled
@@ -280,7 +287,10 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     alpha_pass();
     HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   }
-  hipLaunchKernelGGL((k_gradient<Lat, T, F>), grid, blk, 0, c->stream, a);
+  if (c->slabs)
+    hipLaunchKernelGGL((k_gradient<Lat, T, F, true>), grid, blk, c->slab_bytes, c->stream, a, c->slab_lmax);
+  else
+    hipLaunchKernelGGL((k_gradient<Lat, T, F, false>), grid, blk, 0, c->stream, a, 0);
   hipLaunchKernelGGL((k_interface<Lat, T, F>), grid, blk, 0, c->stream, a, M);
   hipLaunchKernelGGL(k_charge_coef, dim3(nb), blk, 0, c->stream, a.boxes, a.partials, (const double *)a.noz_part,
                      a.scal, M, a.prio);
@@ -317,7 +327,10 @@ elbm_status enqueue_step(elbm_ctx *c, int rec) {
     hipLaunchKernelGGL((k_phi_sub<T, F>), grid, blk, 0, c->stream, a);
   }
   mark(c, ev, 3);
-  hipLaunchKernelGGL((k_efield<Lat, T, F>), grid, blk, 0, c->stream, a);
+  if (c->slabs)
+    hipLaunchKernelGGL((k_efield<Lat, T, F, true>), grid, blk, c->slab_bytes, c->stream, a, c->slab_lmax);
+  else
+    hipLaunchKernelGGL((k_efield<Lat, T, F, false>), grid, blk, 0, c->stream, a, 0);
   mark(c, ev, 4);
   if (fork) {
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
@@ -602,6 +615,16 @@ elbm_status elbm_create(const elbm_params *P, const elbm_box *boxes, int32_t nbo
   c->sor_pairs = true;
   for (const auto &x : c->boxes)
     if ((x.nx & 1) || (int64_t)x.nx * x.ny * x.nz < ((int64_t)1 << 20)) c->sor_pairs = false;
+  {
+    int nxmax = 0;
+    for (const auto &x : c->boxes) nxmax = std::max(nxmax, x.nx);
+    const int lmax = BLK + 2 * (nxmax + 1);
+    const size_t bytes = (size_t)(two_d ? 1 : 3) * lmax * c->esz_fld;
+    if (bytes <= 32768) {  // at most 32 KB per block: the stencils keep their occupancy
+      c->slab_lmax = lmax;
+      c->slab_bytes = bytes;
+    }
+  }
   for (int s = 1; s < NTILE_SHAPES; ++s) {
     int t0 = 0;
     for (int b = 0; b < nboxes; ++b) {
@@ -759,11 +782,15 @@ elbm_status elbm_set_launch(elbm_ctx *c, const elbm_launch *l) {
     return fail(c, ELBM_EINVAL, "graph_steps must be even, 2..64");
   if (l->tile < 0 || l->tile >= NTILE_SHAPES) return fail(c, ELBM_EINVAL, "tile must be 0..3");
   if (l->sweep_priority != 0 && l->sweep_priority != 1) return fail(c, ELBM_EINVAL, "sweep_priority must be 0 or 1");
+  if (l->stencil_lds != 0 && l->stencil_lds != 1) return fail(c, ELBM_EINVAL, "stencil_lds must be 0 or 1");
+  if (l->stencil_lds && !c->slab_lmax)
+    return fail(c, ELBM_EINVAL, "stencil_lds: the LDS slabs of the widest box exceed 32 KB per block");
   if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
   c->remap = l->xcd_remap;
   c->graph_steps = l->graph_steps;
   c->tile = l->tile;
   c->prio = l->sweep_priority;
+  c->slabs = l->stencil_lds != 0;
   c->drop_graphs();  // kernel arguments and step counts are baked into the graphs
   return ELBM_OK;
 }
@@ -774,6 +801,7 @@ elbm_status elbm_get_launch(const elbm_ctx *c, elbm_launch *l) {
   l->graph_steps = c->graph_steps;
   l->tile = c->tile;
   l->sweep_priority = c->prio;
+  l->stencil_lds = c->slabs ? 1 : 0;
   return ELBM_OK;
 }
 
@@ -804,8 +832,8 @@ elbm_status elbm_autotune(elbm_ctx *c, int32_t steps_per_trial, elbm_launch *bes
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  const elbm_launch keep{c->remap, c->graph_steps, c->tile, c->prio};
-  elbm_launch cur{0, 2, 0, 0};
+  const elbm_launch keep{c->remap, c->graph_steps, c->tile, c->prio, c->slabs ? 1 : 0};
+  elbm_launch cur{0, 2, 0, 0, 0};  // the stencils' LDS slabs are not among the candidates
   elbm_status st = ELBM_OK;
   // four passes, each fixing one knob with the winners of the earlier ones:
   // tile shape (4), XCD order (2), field-chain priority (2), graph length

@@ -95,14 +95,58 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a, int inlet_axis) {
   if (inlet_axis >= 0) block_sum_store<2>(acc, a.noz_part + (int64_t)nd.blk * 2);
 }
 
+// LDS slabs of one field around a 256-node block of the linear mapping (a
+// block lies in one box): for each z offset dz of the stencil (-1, 0, +1;
+// 0 only on D2Q9) the box nodes with local index in [n0 + dz P - H,
+// n0 + dz P + BLK + H), P = nx ny, H = nx + 1, which hold every unwrapped
+// lattice neighbour of the block's nodes.  Filled by the whole block with
+// coalesced loads, then read in place of the per-direction global loads; a
+// neighbour outside its slab (a periodic wrap) is read from memory.  A slot
+// holds the value of the node whose index it stands for, so every read is
+// that node's value, whichever way the neighbour index was formed.
+template <typename F, int NS>
+struct FieldSlabs {
+  const F *lds;
+  int lo, L, P, lmax;  // lo: local index of the first slot of the dz = 0 slab
+  __device__ __forceinline__ void fill(F *sm, const F *field, const BoxDev &B, int n0, int lmax_) {
+    lds = sm;
+    lmax = lmax_;
+    P = B.nx * B.ny;
+    const int H = B.nx + 1;
+    L = BLK + 2 * H;
+    lo = n0 - H;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int base = lo + (k - NS / 2) * P;
+      for (int i = threadIdx.x; i < L; i += BLK) {
+        const int idx = base + i;
+        if (idx >= 0 && idx < B.n) sm[k * lmax + i] = field[B.off + idx];
+      }
+    }
+    __syncthreads();
+  }
+  // value of local node m >= 0, a neighbour at z offset dz
+  __device__ __forceinline__ F get(const F *field, const BoxDev &B, int m, int dz) const {
+    const int off = m - (lo + dz * P);
+    return (off >= 0 && off < L) ? lds[(dz + NS / 2) * lmax + off] : field[B.off + m];
+  }
+};
+
 // 19-point isotropic gradient G = (1/c_s^2) sum_p w_p c_p rho_A(r + c_p) (a
 // solid or outside neighbour takes the centre value), stored as the unit
 // normal n = G/|G| (0 where |G| <= 1e-12) and |G|^2.
-template <typename Lat, typename T, typename F>
-__global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
+// STAGE: neighbours from the LDS slabs (lmax: slab stride, the dynamic LDS
+// holds Lat::D == 3 ? 3 : 1 slabs of it).
+template <typename Lat, typename T, typename F, bool STAGE>
+__global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a, int lmax) {
   Node nd;
   decode(a, nd);
   field_chain_priority(a.prio);  // after the uniform loads of decode
+  FieldSlabs<F, Lat::D == 3 ? 3 : 1> sl;
+  if constexpr (STAGE) {
+    extern __shared__ __align__(16) unsigned char slab_mem[];
+    sl.fill(reinterpret_cast<F *>(slab_mem), a.rho, nd.B, (int)(nd.g - threadIdx.x - nd.B.off), lmax);
+  }
   if (!nd.live) return;
   F g0 = F(0), g1 = F(0), g2 = F(0);
   if ((a.type[nd.g] & 3) != K_SOLID) {
@@ -112,7 +156,7 @@ __global__ __launch_bounds__(BLK) void k_gradient(Ptrs<T, F> a) {
     for (int p = 1; p < Lat::Q; ++p) {
       const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
       F v = c;
-      if (m >= 0 && !((msk >> p) & 1u)) v = a.rho[nd.B.off + m];
+      if (m >= 0 && !((msk >> p) & 1u)) v = STAGE ? sl.get(a.rho, nd.B, m, Lat::cz[p]) : a.rho[nd.B.off + m];
       // zero lattice-vector components add nothing: skipped (same sums)
       if (Lat::cx[p]) g0 += F(Lat::w(p) * Lat::cx[p]) * v;
       if (Lat::cy[p]) g1 += F(Lat::w(p) * Lat::cy[p]) * v;
@@ -437,18 +481,23 @@ __global__ __launch_bounds__(BLK) void k_phi_sub(Ptrs<T, F> a) {
 
 // |E|^2 with E = E_ext - grad phi (19-point gradient; an outside neighbour
 // takes the centre value, wall nodes carry their fixed potential).
-template <typename Lat, typename T, typename F>
-__global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a) {
+template <typename Lat, typename T, typename F, bool STAGE>
+__global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a, int lmax) {
   Node nd;
   decode(a, nd);
   field_chain_priority(a.prio);  // after the uniform loads of decode
+  FieldSlabs<F, Lat::D == 3 ? 3 : 1> sl;
+  if constexpr (STAGE) {
+    extern __shared__ __align__(16) unsigned char slab_mem[];
+    sl.fill(reinterpret_cast<F *>(slab_mem), a.phi, nd.B, (int)(nd.g - threadIdx.x - nd.B.off), lmax);
+  }
   if (!nd.live) return;
   const F c = a.phi[nd.g];
   F g0 = F(0), g1 = F(0), g2 = F(0);
 #pragma unroll
   for (int p = 1; p < Lat::Q; ++p) {
     const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
-    const F v = m >= 0 ? a.phi[nd.B.off + m] : c;
+    const F v = m >= 0 ? (STAGE ? sl.get(a.phi, nd.B, m, Lat::cz[p]) : a.phi[nd.B.off + m]) : c;
     g0 += F(Lat::w(p) * Lat::cx[p]) * v;
     g1 += F(Lat::w(p) * Lat::cy[p]) * v;
     g2 += F(Lat::w(p) * Lat::cz[p]) * v;

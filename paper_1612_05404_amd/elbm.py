@@ -61,7 +61,7 @@ class elbm_box(ct.Structure):
 
 class elbm_launch(ct.Structure):
     _fields_ = [("xcd_remap", ct.c_int32), ("graph_steps", ct.c_int32), ("tile", ct.c_int32),
-                ("sweep_priority", ct.c_int32)]
+                ("sweep_priority", ct.c_int32), ("stencil_lds", ct.c_int32)]
 
 
 class elbm_diag(ct.Structure):
@@ -89,7 +89,7 @@ TILES = {0: "linear", 1: "8x8x4", 2: "8x4x8", 3: "4x4x16"}
 PHASES = ["density", "charge", "poisson", "efield", "alpha", "collide"]
 
 _lib = None
-ABI_VERSION = 6  # include/elbm.h ELBM_ABI_VERSION
+ABI_VERSION = 7  # include/elbm.h ELBM_ABI_VERSION
 
 
 def load(path: str = LIB_PATH):
@@ -415,14 +415,15 @@ class Lattice:
         return feat, tgt, scl, val
 
     # ---------------------------------------------------- launch mapping
-    def set_launch(self, xcd_remap: int, graph_steps: int, tile: int = 0, sweep_priority: int = 0):
-        l = elbm_launch(int(xcd_remap), int(graph_steps), int(tile), int(sweep_priority))
+    def set_launch(self, xcd_remap: int, graph_steps: int, tile: int = 0, sweep_priority: int = 0,
+                   stencil_lds: int = 0):
+        l = elbm_launch(int(xcd_remap), int(graph_steps), int(tile), int(sweep_priority), int(stencil_lds))
         self._check(self.L.elbm_set_launch(self.h, ct.byref(l)))
 
     @staticmethod
     def _launch_dict(l) -> dict:
         return {"xcd_remap": l.xcd_remap, "graph_steps": l.graph_steps, "tile": l.tile,
-                "sweep_priority": l.sweep_priority}
+                "sweep_priority": l.sweep_priority, "stencil_lds": l.stencil_lds}
 
     def get_launch(self) -> dict:
         l = elbm_launch()

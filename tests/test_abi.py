@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_abi_version(lib):
     from paper_1612_05404_amd import elbm
-    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 6
+    assert lib.elbm_abi_version() == elbm.ABI_VERSION == 7
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -173,3 +173,37 @@ def test_nozzle_bit_only_on_fluid_nodes(elbm):
         lat.set_box(0, inputs.Box(b.nx, b.ny, b.nz, b.periodic, bad, b.rho0, b.u0, b.phi0, b.u_bc, b.xi, b.jitter))
     assert e.value.status == elbm.ELBM_EINVAL
     lat.close()
+
+
+def _state(lat):
+    rho, u = lat.read_moments(0)
+    return (lat.get_populations(0), lat.read_potential(0), lat.read_charge(0), rho, u)
+
+
+@pytest.mark.parametrize("geometry", ["jet3d", "jet2d", "drop2d"])
+def test_stencil_lds_slabs_are_bit_identical(elbm, geometry):
+    # The launch option stencil_lds (the gradient and E-field stencils read
+    # their neighbours from LDS slabs) changes where values are read, not the
+    # arithmetic: every field equal to the bit after 40 steps, on the jet
+    # geometry (closed axes, Dirichlet planes, inlet, outlet), the 2-D
+    # electrospinning set-up and the periodic 2-D drop (wrapped neighbours
+    # outside the slabs).
+    if geometry == "jet3d":
+        wl = inputs.jet(nx=48, ny=48, nz=96)
+        dtype = "f32"
+    elif geometry == "jet2d":
+        wl = inputs.paper_jet_2d(case="c", n=48, diameter=12, nozzle_len=10, wall=2)
+        dtype = "f64"
+    else:
+        wl = inputs.Workload("drop2d", _paper_params(), [_plane_drop(64, 12.0, seed=11)], "f64", 40)
+        dtype = "f64"
+    _say(f"[gpu slabs] {geometry} {dtype}: stencil_lds 0 vs 1, 40 steps")
+    out = []
+    for lds in (0, 1):
+        lat = elbm.Lattice(wl.params, wl.boxes, dtype, alpha_guess="series")
+        lat.set_launch(0, 2, 0, 0, lds)
+        lat.step(40, record=True)
+        out.append(_state(lat))
+        lat.close()
+    for a, b in zip(*out):
+        assert np.array_equal(np.asarray(a), np.asarray(b))

@@ -59,21 +59,22 @@ def test_launch_mappings_give_identical_results(elbm):
     wl = inputs.ensemble(nboxes=5, edges=(24, 32, 48))
     _say("[gpu ensemble] launch mappings, 5 boxes f32, 24 steps")
     ref = None
-    for remap, gs, tile, prio in ((0, 2, 0, 0), (1, 2, 0, 1), (0, 8, 1, 0), (1, 4, 2, 1), (0, 2, 3, 1),
-                                  (1, 8, 3, 0)):
+    for remap, gs, tile, prio, lds in ((0, 2, 0, 0, 0), (1, 2, 0, 1, 1), (0, 8, 1, 0, 0), (1, 4, 2, 1, 0),
+                                       (0, 2, 3, 1, 1), (1, 8, 3, 0, 0), (0, 2, 0, 0, 1)):
         lat = elbm.Lattice(wl.params, wl.boxes, "f32")
-        lat.set_launch(remap, gs, tile, prio)
-        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs, "tile": tile, "sweep_priority": prio}
+        lat.set_launch(remap, gs, tile, prio, lds)
+        assert lat.get_launch() == {"xcd_remap": remap, "graph_steps": gs, "tile": tile, "sweep_priority": prio,
+                                    "stencil_lds": lds}
         lat.step(24, record=True)
         got = [_fields(lat, i) + (lat.read_alpha(i)[0],) for i in range(len(wl.boxes))]
         if ref is None:
             ref = got
         else:
-            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs, tile, prio)
+            assert all(_same(a, b) for a, b in zip(got, ref)), (remap, gs, tile, prio, lds)
         lat.close()
     lat = elbm.Lattice(wl.params, wl.boxes, "f32")
     try:
-        for bad in ((0, 3, 0), (2, 2, 0), (0, 2, 4), (0, 2, 0, 2)):
+        for bad in ((0, 3, 0), (2, 2, 0), (0, 2, 4), (0, 2, 0, 2), (0, 2, 0, 0, 2)):
             with pytest.raises(elbm.ElbmError):
                 lat.set_launch(*bad)
     finally:
