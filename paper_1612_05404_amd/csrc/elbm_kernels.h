@@ -639,9 +639,10 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         f[p * BLK] = v;
         const double dv = double(v);
         dr += dv;
-        jx += double(Lat::cx[p]) * dv;
-        jy += double(Lat::cy[p]) * dv;
-        jz += double(Lat::cz[p]) * dv;
+        // only the nonzero components (+-dv exactly; a zero term adds +-0)
+        if (Lat::cx[p]) jx += double(Lat::cx[p]) * dv;
+        if (Lat::cy[p]) jy += double(Lat::cy[p]) * dv;
+        if (Lat::cz[p]) jz += double(Lat::cz[p]) * dv;
       }
     }
     // divisions, not one reciprocal: every instantiation (plain, learned)
@@ -689,13 +690,15 @@ __global__ __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) void k_alpha(Ptrs<T, F
         double P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
 #pragma unroll  // fully: the lattice vectors fold and the LDS reads issue together
         for (int p = 0; p < Lat::Q; ++p) {
+          // only the nonzero products c_a c_b = +-1 are summed (+-f exactly;
+          // a zero term would add +-0 and leave the sum as it is)
           const double d = double(f[p * BLK]);
-          P00 += d * double(Lat::cx[p] * Lat::cx[p]);
-          P11 += d * double(Lat::cy[p] * Lat::cy[p]);
-          P22 += d * double(Lat::cz[p] * Lat::cz[p]);
-          P01 += d * double(Lat::cx[p] * Lat::cy[p]);
-          P02 += d * double(Lat::cx[p] * Lat::cz[p]);
-          P12 += d * double(Lat::cy[p] * Lat::cz[p]);
+          if (Lat::cx[p] * Lat::cx[p]) P00 += d;
+          if (Lat::cy[p] * Lat::cy[p]) P11 += d;
+          if (Lat::cz[p] * Lat::cz[p]) P22 += d;
+          if (Lat::cx[p] * Lat::cy[p]) P01 += double(Lat::cx[p] * Lat::cy[p]) * d;
+          if (Lat::cx[p] * Lat::cz[p]) P02 += double(Lat::cx[p] * Lat::cz[p]) * d;
+          if (Lat::cy[p] * Lat::cz[p]) P12 += double(Lat::cy[p] * Lat::cz[p]) * d;
         }
         P00 -= dr * (CS2 + ux * ux);
         P11 -= dr * (CS2 + uy * uy);
@@ -814,9 +817,10 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
                     : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + m];
       const double dv = double(f[p]);
       dr += dv;
-      jx += double(Lat::cx[p]) * dv;
-      jy += double(Lat::cy[p]) * dv;
-      jz += double(Lat::cz[p]) * dv;
+      // only the nonzero components (+-dv exactly; a zero term adds +-0)
+      if (Lat::cx[p]) jx += double(Lat::cx[p]) * dv;
+      if (Lat::cy[p]) jy += double(Lat::cy[p]) * dv;
+      if (Lat::cz[p]) jz += double(Lat::cz[p]) * dv;
     }
     const double ird = rcp_nr(dr);  // one reciprocal for the three components
     const double ux = jx * ird, uy = jy * ird, uz = jz * ird;
@@ -842,8 +846,10 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
 #pragma unroll
     for (int p = 0; p < Lat::Q; ++p) {
       const double fe = feq<Lat, double>(p, dr, ux, uy, uz, uu);
-      const double cd = double(Lat::cx[p]) * dx_ + double(Lat::cy[p]) * dy_ + double(Lat::cz[p]) * dz_;
-      const double cs = double(Lat::cx[p]) * sx + double(Lat::cy[p]) * sy + double(Lat::cz[p]) * sz;
+      // c.d and c.s over the nonzero components only (c_a = +-1: the same
+      // sums without the zero terms)
+      const double cd = cdot<double>(Lat::cx[p], Lat::cy[p], Lat::cz[p], dx_, dy_, dz_);
+      const double cs = cdot<double>(Lat::cx[p], Lat::cy[p], Lat::cz[p], sx, sy, sz);
       const double src = Lat::w(p) * dr * (3.0 * cd + 4.5 * (cd * cs) - 1.5 * ds);
       const double fp = double(f[p]);
       const double v = fp + ab * (fe - fp) + src;
