@@ -498,9 +498,10 @@ __global__ __launch_bounds__(BLK) void k_efield(Ptrs<T, F> a, int lmax) {
   for (int p = 1; p < Lat::Q; ++p) {
     const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
     const F v = m >= 0 ? (STAGE ? sl.get(a.phi, nd.B, m, Lat::cz[p]) : a.phi[nd.B.off + m]) : c;
-    g0 += F(Lat::w(p) * Lat::cx[p]) * v;
-    g1 += F(Lat::w(p) * Lat::cy[p]) * v;
-    g2 += F(Lat::w(p) * Lat::cz[p]) * v;
+    // zero lattice-vector components add nothing: skipped (same sums)
+    if (Lat::cx[p]) g0 += F(Lat::w(p) * Lat::cx[p]) * v;
+    if (Lat::cy[p]) g1 += F(Lat::w(p) * Lat::cy[p]) * v;
+    if (Lat::cz[p]) g2 += F(Lat::w(p) * Lat::cz[p]) * v;
   }
   const F e0 = F(nd.B.E[0]) - g0 / F(CS2), e1 = F(nd.B.E[1]) - g1 / F(CS2), e2 = F(nd.B.E[2]) - g2 / F(CS2);
   a.e2[nd.g] = e0 * e0 + e1 * e1 + e2 * e2;
@@ -762,10 +763,11 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
       const int m = nbr(nd.B, nd.x, nd.y, nd.z, Lat::cx[p], Lat::cy[p], Lat::cz[p]);
       const int64_t gm = nd.B.off + (m >= 0 ? m : nd.n);
       if (m < 0) solid |= 1u << p;  // outside the box: already in the mask; kept as a guard
+      // zero lattice-vector components add nothing: skipped (same sums)
       if ((solid >> p) & 1u) {
-        wall[0] += F(Lat::w(p) * Lat::cx[p]);
-        wall[1] += F(Lat::w(p) * Lat::cy[p]);
-        wall[2] += F(Lat::w(p) * Lat::cz[p]);
+        if (Lat::cx[p]) wall[0] += F(Lat::w(p) * Lat::cx[p]);
+        if (Lat::cy[p]) wall[1] += F(Lat::w(p) * Lat::cy[p]);
+        if (Lat::cz[p]) wall[2] += F(Lat::w(p) * Lat::cz[p]);
       } else {
         F ps[C];
 #pragma unroll
@@ -775,19 +777,19 @@ __global__ __launch_bounds__(BLK) void k_collide(Ptrs<T, F> a, Model M, int reco
           F sp = F(0);
 #pragma unroll
           for (int t = 0; t < C; ++t) sp += F(M.G[s][t]) * ps[t];
-          acc[s][0] += F(Lat::w(p)) * sp * F(Lat::cx[p]);
-          acc[s][1] += F(Lat::w(p)) * sp * F(Lat::cy[p]);
-          acc[s][2] += F(Lat::w(p)) * sp * F(Lat::cz[p]);
+          if (Lat::cx[p]) acc[s][0] += F(Lat::w(p)) * sp * F(Lat::cx[p]);
+          if (Lat::cy[p]) acc[s][1] += F(Lat::w(p)) * sp * F(Lat::cy[p]);
+          if (Lat::cz[p]) acc[s][2] += F(Lat::w(p)) * sp * F(Lat::cz[p]);
         }
       }
       const F vp = m >= 0 ? a.phi[gm] : phic;
       const F ve = m >= 0 ? a.e2[gm] : e2c;
-      gp[0] += F(Lat::w(p) * Lat::cx[p]) * vp;
-      gp[1] += F(Lat::w(p) * Lat::cy[p]) * vp;
-      gp[2] += F(Lat::w(p) * Lat::cz[p]) * vp;
-      ge[0] += F(Lat::w(p) * Lat::cx[p]) * ve;
-      ge[1] += F(Lat::w(p) * Lat::cy[p]) * ve;
-      ge[2] += F(Lat::w(p) * Lat::cz[p]) * ve;
+      if (Lat::cx[p]) gp[0] += F(Lat::w(p) * Lat::cx[p]) * vp;
+      if (Lat::cy[p]) gp[1] += F(Lat::w(p) * Lat::cy[p]) * vp;
+      if (Lat::cz[p]) gp[2] += F(Lat::w(p) * Lat::cz[p]) * vp;
+      if (Lat::cx[p]) ge[0] += F(Lat::w(p) * Lat::cx[p]) * ve;
+      if (Lat::cy[p]) ge[1] += F(Lat::w(p) * Lat::cy[p]) * ve;
+      if (Lat::cz[p]) ge[2] += F(Lat::w(p) * Lat::cz[p]) * ve;
     }
     const F qn = a.q[nd.g];
     const F rA = a.rho[nd.g];
