@@ -72,6 +72,11 @@ __global__ __launch_bounds__(BLK) void k_density(Ptrs<T, F> a, int inlet_axis) {
       if (k == K_INLET || k == K_OUTLET) {
 #pragma unroll
         for (int p = 0; p < Lat::Q; ++p) r += F(a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.g]);
+      } else if (k == K_FLUID && inlet_axis < 0) {  // no nozzle sums (a uniform choice: one plain loop)
+#pragma unroll
+        for (int p = 0; p < Lat::Q; ++p)
+          r += F(bb[p] ? a.fa[(int64_t)(s * Lat::Q + opp(p)) * a.N + nd.g]
+                       : a.fa[(int64_t)(s * Lat::Q + p) * a.N + nd.B.off + src[p]]);
       } else if (k == K_FLUID) {
 #pragma unroll
         for (int p = 0; p < Lat::Q; ++p) {
