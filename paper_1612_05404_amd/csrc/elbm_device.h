@@ -510,11 +510,11 @@ constexpr double QUIET_X = 5e-4;
 
 // Moments M_2 .. M_{D+1} of one node from its x and f columns and the
 // entropy term L = sum_p Delta_p ln(f_p / (w_p rho)) (fixed order p = 0..Q-1;
-// Delta_p recomputed exactly as in the set-up pass).  NEAR0: the logarithm
+// Delta_p = x_p f_p, from the stored x_p = Delta_p / f_p rather than a second
+// evaluation of the equilibrium: the same to rounding).  NEAR0: the logarithm
 // takes its Taylor series where |y| < 1/32.
 template <typename Lat, typename T, int D, bool NEAR0>
-__device__ __forceinline__ double series_moments(const T *f, const double *xs, double *M, double rho, double irho,
-                                                 double ux, double uy, double uz, double uu) {
+__device__ __forceinline__ double series_moments(const T *f, const double *xs, double *M, double rho, double irho) {
 #pragma unroll
   for (int k = 0; k < D; ++k) M[k] = 0.0;
   double L = 0.0;
@@ -529,7 +529,7 @@ __device__ __forceinline__ double series_moments(const T *f, const double *xs, d
       t *= x;
     }
     const double wr = Lat::w(p) * rho;
-    const double d = feq<Lat, double>(p, rho, ux, uy, uz, uu) - fp;
+    const double d = x * fp;
     const double y = (fp - wr) * (irho * (1.0 / Lat::w(p)));
     L += d * (NEAR0 ? log1p_near0(y) : log1p_fast(y));
   }
@@ -605,9 +605,9 @@ __device__ __forceinline__ AlphaSetup alpha_setup(const T *f, double *xs, double
   double M[SERIES_DEG];
   const bool quiet = series && __all(xmax < QUIET_X);
   double L;
-  if (quiet) L = series_moments<Lat, T, QUIET_DEG, true>(f, xs, M, rho, irho, ux, uy, uz, uu);
-  else if (series) L = series_moments<Lat, T, SERIES_DEG, false>(f, xs, M, rho, irho, ux, uy, uz, uu);
-  else L = series_moments<Lat, T, 1, false>(f, xs, M, rho, irho, ux, uy, uz, uu);
+  if (quiet) L = series_moments<Lat, T, QUIET_DEG, true>(f, xs, M, rho, irho);
+  else if (series) L = series_moments<Lat, T, SERIES_DEG, false>(f, xs, M, rho, irho);
+  else L = series_moments<Lat, T, 1, false>(f, xs, M, rho, irho);
   st.L = L;
   st.M2 = M[0];
   if (xmax < 1e-12) {
