@@ -26,3 +26,15 @@ def test_algorithmic_bytes_per_node():
     assert bench.collide_bytes_per_node(4, 4, 2) == 304 + 16 + 28 + 1
     # whole step with k SOR sweeps
     assert bench.step_bytes_per_node(4, 2, 8) == 304 + 40 + 128
+
+
+def test_ensemble_comparison_starts_where_the_autotuner_leaves_the_state():
+    # the comparison starters run as many warm-up steps as the autotuner
+    # advances the learned run: two rounds over each of its candidates of 32
+    # steps, plus one graph replay before each trial (elbm_autotune)
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1612_05404_amd import elbm
+    assert elbm.TUNE_CANDIDATES == 11
+    graph_warmups = 2 * (4 + 2 + 2) * 2 + 2 * (2 + 4 + 8)
+    assert bench.AUTOTUNE_STEPS == 2 * elbm.TUNE_CANDIDATES * 32 + graph_warmups == 764
